@@ -1,0 +1,354 @@
+"""Seeded synthetic workloads for banded seed extension.
+
+This module only draws inputs: sequences, seed scores and scoring sets.  It
+holds none of the extension's arithmetic and serves the GPU library and the
+oracle alike.  The paper's read sets and the pairs it intercepted from
+BWA-MEM (Sec. 6.1.2, Table 3; Table 6) are not available, so every workload
+is a stand-in with read-shaped statistics:
+
+* a query is the part of a read left of or right of a seed, drawn as
+  uniform random ACGT (codes 0..3);
+* its target is the query passed through a mutation walk (substitutions,
+  and insertions or deletions of geometric length) and followed by random
+  reference flank, since the target window reaches past the read end;
+* ambiguous bases N (code 4) are sprinkled in where a workload asks for it;
+* the seed score h0 is uniform in [19, 50] (a seed of 19-50 matching bases
+  at match score 1);
+* the RNG is NumPy's PCG64 seeded with the workload index.
+
+A batch is a dict of NumPy arrays: ``q`` (u8 codes), ``q_off`` (u64, n+1),
+``t`` (u8), ``t_off`` (u64, n+1), ``h0`` (i32), ``param_id`` (u8, or
+absent for a single scoring set) and ``scorings`` (list of dicts).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def scoring(match=1, mismatch=-4, n_score=-1, o=6, e=1, w=100, zdrop=100,
+            end_bonus=5, o_ins=None, e_ins=None):
+    """A scoring set in the library's layout: mat[target][query]."""
+    mat = np.full((5, 5), mismatch, dtype=np.int64)
+    np.fill_diagonal(mat, match)
+    mat[4, :] = n_score
+    mat[:, 4] = n_score
+    return {"mat": mat.tolist(), "o_del": o, "e_del": e,
+            "o_ins": o if o_ins is None else o_ins,
+            "e_ins": e if e_ins is None else e_ins,
+            "w": w, "zdrop": zdrop, "end_bonus": end_bonus}
+
+
+BWA_DEFAULT = scoring()  # match 1, mismatch -4, N -1, gap 6+k*1, w 100, z 100, bonus 5
+WIDE_A = scoring(1, -4, -1, 6, 1, w=500, zdrop=400, end_bonus=5)
+WIDE_B = scoring(2, -3, -1, 5, 2, w=500, zdrop=400, end_bonus=5)
+
+
+# ---------------------------------------------------------------------------
+# vectorised building blocks (all on flat concatenated arrays)
+
+def _offsets(lengths):
+    off = np.zeros(len(lengths) + 1, dtype=np.uint64)
+    np.cumsum(lengths, out=off[1:])
+    return off
+
+
+def _pair_index(lengths):
+    return np.repeat(np.arange(len(lengths), dtype=np.int64), lengths)
+
+
+def _random_bases(rng, n):
+    return rng.integers(0, 4, size=n, dtype=np.uint8)
+
+
+def _mutate(rng, seq, lengths, p_sub, p_indel, mean_len):
+    """Mutation walk over every pair's sequence at once.
+
+    Per position: with probability p_sub (per pair) the base becomes a
+    different base chosen uniformly; independently, with probability
+    p_indel an indel starts there: a deletion of the next k bases or an
+    insertion of k random bases after it (1/2 each), k ~ Geometric(1/mean).
+    Returns (mutated flat array, new lengths)."""
+    n = len(seq)
+    pid = _pair_index(lengths)
+    out = seq.copy()
+    sub = rng.random(n) < p_sub[pid]
+    out[sub] = (out[sub] + rng.integers(1, 4, size=int(sub.sum()),
+                                        dtype=np.uint8)) % 4
+    ev = np.nonzero(rng.random(n) < p_indel[pid])[0]
+    ins = np.zeros(n, dtype=np.int64)
+    keep = np.ones(n, dtype=bool)
+    if len(ev):
+        k = rng.geometric(1.0 / mean_len, size=len(ev)).astype(np.int64)
+        is_del = rng.random(len(ev)) < 0.5
+        ends = _offsets(lengths).astype(np.int64)[pid[ev] + 1]
+        # deletions: mark (ev, ev+k] inside the pair as removed
+        de, dk, dend = ev[is_del], k[is_del], ends[is_del]
+        diff = np.zeros(n + 1, dtype=np.int64)
+        lo = np.minimum(de + 1, dend)
+        hi = np.minimum(de + 1 + dk, dend)
+        np.add.at(diff, lo, 1)
+        np.add.at(diff, hi, -1)
+        keep = np.cumsum(diff[:-1]) == 0
+        np.add.at(ins, ev[~is_del], k[~is_del])
+    slots = keep.astype(np.int64) + ins
+    new_len = np.bincount(pid, weights=slots, minlength=len(lengths))
+    start = np.cumsum(slots) - slots
+    res = _random_bases(rng, int(slots.sum()))
+    res[start[keep]] = out[keep]
+    return res, new_len.astype(np.int64)
+
+
+def _join(parts_a, len_a, parts_b, len_b, cap=None):
+    """Per pair: a followed by b, truncated to cap (per pair) if given."""
+    n = len(len_a)
+    tot = len_a + len_b
+    if cap is not None:
+        tot = np.minimum(tot, cap)
+    off_a = _offsets(len_a).astype(np.int64)
+    off_b = _offsets(len_b).astype(np.int64)
+    out_off = _offsets(tot)
+    pid = _pair_index(tot)
+    pos = np.arange(int(tot.sum()), dtype=np.int64) - out_off[:-1].astype(np.int64)[pid]
+    from_a = pos < len_a[pid]
+    out = np.empty(len(pos), dtype=np.uint8)
+    out[from_a] = parts_a[off_a[pid[from_a]] + pos[from_a]]
+    nb = ~from_a
+    out[nb] = parts_b[off_b[pid[nb]] + pos[nb] - len_a[pid[nb]]]
+    return out, tot
+
+
+def _sprinkle_n(rng, seq, p):
+    if p > 0:
+        seq[rng.random(len(seq)) < p] = 4
+    return seq
+
+
+def _assemble(chunks, scorings):
+    qs, ts, qls, tls, h0s, pids = zip(*chunks)
+    ql = np.concatenate(qls)
+    tl = np.concatenate(tls)
+    b = {"q": np.concatenate(qs), "q_off": _offsets(ql),
+         "t": np.concatenate(ts), "t_off": _offsets(tl),
+         "h0": np.concatenate(h0s).astype(np.int32), "scorings": scorings}
+    if pids[0] is not None:
+        b["param_id"] = np.concatenate(pids).astype(np.uint8)
+    return b
+
+
+def _read_pairs(rng, qlen, p_sub, p_indel, mean_len, flank, cap, p_n, h0_range):
+    q = _random_bases(rng, int(qlen.sum()))
+    mut, mlen = _mutate(rng, q, qlen, p_sub, p_indel, mean_len)
+    fl = _random_bases(rng, int(flank.sum()))
+    t, tlen = _join(mut, mlen, fl, flank, cap)
+    q = _sprinkle_n(rng, q, p_n)
+    t = _sprinkle_n(rng, t, p_n)
+    h0 = rng.integers(h0_range[0], h0_range[1] + 1, size=len(qlen))
+    return q, t, qlen, tlen, h0
+
+
+# ---------------------------------------------------------------------------
+# workloads
+
+def plain_small(n=1000, seed=0):
+    """1,000 pairs: query of 101 uniform ACGT; target = query mutated at 2%
+    substitutions and 0.2% indels (geometric, mean 2) + 50 flank bases;
+    h0 in [19, 50]; BWA-MEM default scoring, w 100, z-drop 100, bonus 5."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    qlen = np.full(n, 101, dtype=np.int64)
+    q, t, ql, tl, h0 = _read_pairs(
+        rng, qlen, np.full(n, 0.02), np.full(n, 0.002), 2.0,
+        np.full(n, 50, dtype=np.int64), None, 0.0, (19, 50))
+    return _assemble([(q, t, ql, tl, h0, None)], [BWA_DEFAULT])
+
+
+def read_scale(n=1_000_000, seed=1, chunk=250_000):
+    """Extension remainders of simulated 151 bp reads: qlen uniform in
+    [1, 150]; per pair substitutions 1-5% and indels 0.1-1%; target = mutated
+    query + flank, total qlen + U[0, 200] (2w); 1% of bases N."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    chunks = []
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        qlen = rng.integers(1, 151, size=m).astype(np.int64)
+        extra = rng.integers(0, 201, size=m).astype(np.int64)
+        p_sub = rng.uniform(0.01, 0.05, size=m)
+        p_ind = rng.uniform(0.001, 0.01, size=m)
+        # flank long enough that truncation to qlen + extra always applies
+        flank = extra + 60
+        q, t, ql, tl, h0 = _read_pairs(rng, qlen, p_sub, p_ind, 2.0, flank,
+                                       qlen + extra, 0.01, (19, 50))
+        chunks.append((q, t, ql, tl, h0, None))
+    return _assemble(chunks, [BWA_DEFAULT])
+
+
+def _zdrop_pairs(rng, m):
+    """Pairs built to end by the drop-from-best rule (z-drop 100): an exact
+    prefix of p bases lifts the score to h0 + p >= ~115, then a tail where
+    the target repeats the query with substitutions at 3 of every 8
+    positions loses 7/8 of a point per row along the diagonal.  That is
+    slower than a deletion run (1 per row), so the diagonal stays the row
+    maximum with no drift, and more than 100 below the best after ~115
+    rows, before any row empties."""
+    qlen = rng.integers(220, 251, size=m).astype(np.int64)
+    h0 = rng.integers(19, 51, size=m).astype(np.int64)
+    p = np.maximum(115 - h0, 0) + rng.integers(0, 6, size=m)
+    p = np.minimum(p, qlen - 125)
+    q = _random_bases(rng, int(qlen.sum()))
+    pid = _pair_index(qlen)
+    pos = np.arange(len(q), dtype=np.int64) - _offsets(qlen).astype(np.int64)[pid]
+    tail = pos - p[pid]
+    r = tail % 8
+    sub = (tail >= 0) & ((r == 1) | (r == 4) | (r == 6))
+    tq = q.copy()
+    tq[sub] = (tq[sub] + rng.integers(1, 4, size=int(sub.sum()),
+                                      dtype=np.uint8)) % 4
+    extra = rng.integers(0, 201, size=m).astype(np.int64)
+    fl = _random_bases(rng, int(extra.sum()))
+    t, tlen = _join(tq, qlen, fl, extra)
+    return q, t, qlen, tlen, h0
+
+
+def batched_mix(n=4_000_000, seed=2, chunk=250_000, zdrop_frac=0.20):
+    """Uneven pairs from 100/150/250 bp read sources (one third each):
+    qlen uniform in [1, L]; divergence d uniform in [0, 15%], 0.9 d as
+    substitutions and 0.1 d as indels (geometric, mean 2); target = mutated
+    query + flank, total at most qlen + 200.  A fraction zdrop_frac of the
+    pairs are built to end by z-drop (see _zdrop_pairs); positions of those
+    pairs in the batch are random."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    chunks = []
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        nz = int(round(m * zdrop_frac))
+        nr = m - nz
+        src = rng.choice(np.array([100, 150, 250]), size=nr)
+        qlen = (rng.random(nr) * src).astype(np.int64) + 1
+        d = rng.uniform(0.0, 0.15, size=nr)
+        extra = rng.integers(0, 201, size=nr).astype(np.int64)
+        q1, t1, ql1, tl1, h01 = _read_pairs(
+            rng, qlen, 0.9 * d, 0.1 * d, 2.0, extra + 60, qlen + extra, 0.0,
+            (19, 50))
+        q2, t2, ql2, tl2, h02 = _zdrop_pairs(rng, nz)
+        # interleave the two groups in random order
+        order = rng.permutation(m)
+        ql = np.concatenate([ql1, ql2])
+        tl = np.concatenate([tl1, tl2])
+        qa = np.concatenate([q1, q2])
+        ta = np.concatenate([t1, t2])
+        qo = _offsets(ql).astype(np.int64)
+        to = _offsets(tl).astype(np.int64)
+        qlo, tlo = ql[order], tl[order]
+        qi = _gather_ranges(qo, order, qlo)
+        ti = _gather_ranges(to, order, tlo)
+        h0 = np.concatenate([h01, h02])[order]
+        chunks.append((qa[qi], ta[ti], qlo, tlo, h0, None))
+    return _assemble(chunks, [BWA_DEFAULT])
+
+
+def _gather_ranges(off, order, lens):
+    """Flat indices of ranges [off[k], off[k+1]) for k in order."""
+    starts = off[order]
+    pid = _pair_index(lens)
+    base = _offsets(lens).astype(np.int64)
+    return starts[pid] + np.arange(int(lens.sum()), dtype=np.int64) - base[:-1][pid]
+
+
+def wide_band(n=500_000, seed=4, chunk=100_000):
+    """250 bp queries against targets of up to 750 bp, w 500, z-drop 400,
+    two scoring sets (match 1 / mismatch -4 / gap 6+k; match 2 / mismatch
+    -3 / gap 5+2k) chosen per pair with probability 1/2; 10% of pairs are
+    indel-rich (runs of 1-50 bp, about one per 50 bp)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    chunks = []
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        qlen = np.full(m, 250, dtype=np.int64)
+        rich = rng.random(m) < 0.10
+        p_sub = np.where(rich, 0.02, rng.uniform(0.0, 0.05, size=m))
+        p_ind = np.where(rich, 0.02, rng.uniform(0.001, 0.01, size=m))
+        q = _random_bases(rng, int(qlen.sum()))
+        # rich pairs: geometric mean 25 (runs mostly within 1..50)
+        mut_n, ml_n = _mutate(rng, q, qlen, np.where(rich, 0, p_sub),
+                              np.where(rich, 0, p_ind), 2.0)
+        mut_r, ml_r = _mutate(rng, q, qlen, np.where(rich, p_sub, 0),
+                              np.where(rich, p_ind, 0), 25.0)
+        mut, ml = _pick(rich, mut_n, ml_n, mut_r, ml_r)
+        flank = rng.integers(0, 501, size=m).astype(np.int64)
+        fl = _random_bases(rng, int(flank.sum()))
+        t, tlen = _join(mut, ml, fl, flank, np.full(m, 750, dtype=np.int64))
+        h0 = rng.integers(19, 51, size=m)
+        pid = (rng.random(m) < 0.5).astype(np.uint8)
+        chunks.append((q, t, qlen, tlen, h0, pid))
+    return _assemble(chunks, [WIDE_A, WIDE_B])
+
+
+def _pick(mask, a, la, b, lb):
+    """Per pair: sequence from b where mask else from a."""
+    lens = np.where(mask, lb, la)
+    oa = _offsets(la).astype(np.int64)
+    ob = _offsets(lb).astype(np.int64)
+    pid = _pair_index(lens)
+    pos = np.arange(int(lens.sum()), dtype=np.int64) - _offsets(lens).astype(np.int64)[:-1][pid]
+    m = mask[pid]
+    out = np.empty(len(pos), dtype=np.uint8)
+    out[~m] = a[oa[pid[~m]] + pos[~m]]
+    out[m] = b[ob[pid[m]] + pos[m]]
+    return out, lens
+
+
+def serving_requests(n_requests=2000, seed=3, lo=1000, hi=100_000):
+    """Request sizes log-uniform in [lo, hi] pairs; each request is drawn
+    like the uneven batched mix (its own chunk of the same generator)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_requests))
+    return sizes.astype(np.int64)
+
+
+WORKLOADS = {
+    "plain_small": plain_small,
+    "read_scale": read_scale,
+    "batched_mix": batched_mix,
+    "wide_band": wide_band,
+}
+
+
+def subset(batch, idx):
+    """The pairs idx of a batch, as a new batch (same scoring sets)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    qo = batch["q_off"].astype(np.int64)
+    to = batch["t_off"].astype(np.int64)
+    ql = qo[idx + 1] - qo[idx]
+    tl = to[idx + 1] - to[idx]
+    out = {"q": batch["q"][_gather_ranges(qo, idx, ql)] if len(idx) else batch["q"][:0],
+           "q_off": _offsets(ql),
+           "t": batch["t"][_gather_ranges(to, idx, tl)] if len(idx) else batch["t"][:0],
+           "t_off": _offsets(tl),
+           "h0": batch["h0"][idx].copy(), "scorings": batch["scorings"]}
+    if "param_id" in batch:
+        out["param_id"] = batch["param_id"][idx].copy()
+    return out
+
+
+def from_pairs(pairs, scorings, param_id=None):
+    """Batch from a list of (q codes, t codes, h0)."""
+    ql = np.array([len(p[0]) for p in pairs], dtype=np.int64)
+    tl = np.array([len(p[1]) for p in pairs], dtype=np.int64)
+    b = {"q": np.array([c for p in pairs for c in p[0]], dtype=np.uint8),
+         "q_off": _offsets(ql),
+         "t": np.array([c for p in pairs for c in p[1]], dtype=np.uint8),
+         "t_off": _offsets(tl),
+         "h0": np.array([p[2] for p in pairs], dtype=np.int32),
+         "scorings": list(scorings)}
+    if param_id is not None:
+        b["param_id"] = np.asarray(param_id, dtype=np.uint8)
+    return b
+
+
+def pair(batch, k):
+    """(q codes, t codes, h0, scoring) of pair k."""
+    qo, to = batch["q_off"], batch["t_off"]
+    sc = batch["scorings"][int(batch["param_id"][k]) if "param_id" in batch else 0]
+    return (batch["q"][int(qo[k]):int(qo[k + 1])],
+            batch["t"][int(to[k]):int(to[k + 1])], int(batch["h0"][k]), sc)
