@@ -1,0 +1,164 @@
+/*
+ * bsw.h -- C ABI of libbsw.so: banded Smith-Waterman seed extension (BSW)
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper Sec. 5.1, Eq. (2) and (3); rules (a)-(c) of
+ * Sec. 5.1; outputs of Sec. 5.4 (a),(b)): for each pair (query q, target t,
+ * seed score h0) extend the seed by affine-gap dynamic programming over a
+ * band around the diagonal, one target position per row and one query
+ * position per column, stopping when a row is all zero or has dropped
+ * further than z-drop below the best score, and narrowing the band after
+ * each row by its empty cells at both ends.  Readings of the points the
+ * paper leaves open (gap cost o + k*e with gaps opening from the diagonal
+ * term, positive-diagonal gating, boundary rows, tie rules, band cap by the
+ * end bonus) are documented with the implementation; every result is
+ * bit-identical to the reference implementation of those rules.
+ *
+ * Conventions for every entry point:
+ *  - Sequences are byte codes 0..3 = A,C,G,T and 4 = N, concatenated; pair
+ *    k's query is q[q_off[k] .. q_off[k+1]) and its target
+ *    t[t_off[k] .. t_off[k+1]).  Offsets are non-decreasing uint64.
+ *  - Lengths are at most BSW_MAX_LEN; 1 <= h0 <= BSW_MAX_H0.
+ *  - param_id[k] selects params[param_id[k]] (n_params <= 256); a NULL
+ *    param_id means set 0 for every pair.
+ *  - The caller owns every input and output buffer.  The library keeps no
+ *    pointer to them once a call has returned (blocking calls) or once the
+ *    stream has passed the enqueued work (asynchronous calls).  It owns only
+ *    its context (device arena, streams, events).
+ *  - Errors are negative status codes; bsw_last_error() describes the most
+ *    recent one of the calling thread.  On an error no output is written.
+ *  - n = 0 is a no-op that returns BSW_OK.
+ *  - One context per host thread (a context is not thread-safe).
+ */
+#ifndef BSW_H
+#define BSW_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BSW_ABI_VERSION 1
+
+#define BSW_MAX_LEN   65535
+#define BSW_MAX_H0    (1 << 24)
+#define BSW_MAX_GAP   1000      /* max o_* and e_*                      */
+#define BSW_MAX_BONUS (1 << 24)
+
+/* One scoring set (56 bytes).  mat[a*5+b] scores target code a against
+ * query code b.  A gap of length k >= 1 costs o + k*e; deletions consume
+ * target only, insertions query only.  Requirements: 0 <= o <= 1000,
+ * 1 <= e <= 1000, w >= 0, 0 <= end_bonus <= 2^24; zdrop <= 0 disables the
+ * drop-from-best abort.  The end bonus only narrows the band:
+ * w' = min(w, cap_ins, cap_del), cap = (qlen*A + end_bonus - o)/e + 1 with
+ * A = max(0, max mat). */
+typedef struct bsw_params {
+  int8_t  mat[25];
+  int8_t  pad_[3];
+  int32_t o_del, e_del, o_ins, e_ins;
+  int32_t w;
+  int32_t zdrop;
+  int32_t end_bonus;
+} bsw_params;
+
+/* Per-pair result (24 bytes). */
+typedef struct bsw_result {
+  int32_t score;   /* best score; h0 when nothing beat the seed            */
+  int32_t qle;     /* 1-based query end of the best cell; 0 = none         */
+  int32_t tle;     /* 1-based target end of the best cell; 0 = none        */
+  int32_t gtle;    /* 1-based target end where gscore was reached; 0 = never */
+  int32_t gscore;  /* best score reaching the query end; -1 = never        */
+  int32_t max_off; /* largest |column - row| over improving cells          */
+} bsw_result;
+
+/* Optional per-pair diagnostics (16 bytes). */
+typedef struct bsw_diag {
+  int32_t rows;    /* rows entered, the stopping row included              */
+  int32_t stop;    /* 0 = target exhausted, 1 = all-zero row, 2 = z-drop   */
+  int64_t cells;   /* band cells computed over those rows                  */
+} bsw_diag;
+
+enum {
+  BSW_OK = 0,
+  BSW_EINVAL = -1,  /* bad argument or pair (see bsw_last_error)           */
+  BSW_ENOMEM = -2,  /* device or host allocation failed                    */
+  BSW_EDEVICE = -3, /* no usable gfx950 device, or a HIP call failed       */
+  BSW_ETOOBIG = -4, /* request larger than the context's HBM budget        */
+  BSW_EBUSY = -5,   /* serving: no free slot within the timeout            */
+  BSW_ETIMEOUT = -6 /* serving: ticket not complete within the timeout     */
+};
+
+/* Execution path used by a call. */
+enum {
+  BSW_PATH_BATCHED = 0, /* length binning + persistent longest-first tile
+                         * queues; the default                              */
+  BSW_PATH_PLAIN = 1    /* length binning + one ordinary launch per bin     */
+};
+
+typedef struct bsw_ctx bsw_ctx;
+
+/* Options for bsw_ctx_create (zero-initialise, then set what you need). */
+typedef struct bsw_ctx_opts {
+  int32_t device;          /* HIP device ordinal                           */
+  int32_t min_lane_bits;   /* 0 = pick 8/16/32 from each pair's score bound;
+                            * 16 or 32 forces at least that width           */
+  int32_t force_mode;      /* 0 = by length, 1 = lane mode, 2 = wave mode   */
+  int32_t path;            /* BSW_PATH_BATCHED or BSW_PATH_PLAIN            */
+  size_t  hbm_budget;      /* arena cap in bytes; 0 = 8 GiB                 */
+  const char* tune_cache;  /* autotuner JSON cache path, or NULL            */
+} bsw_ctx_opts;
+
+/* Create a context on a device.  Returns BSW_EDEVICE when the device is
+ * missing or is not gfx950.  *out is set only on success. */
+int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts);
+void bsw_ctx_destroy(bsw_ctx* ctx);
+
+/* Host-memory batch: validates every argument first, stages the inputs
+ * into the context's device arena, runs the extension and copies the
+ * results (and diagnostics when diag != NULL) back.  Blocking. */
+int bsw_extend_batch(bsw_ctx* ctx, int64_t n,
+                     const uint8_t* q, const uint64_t* q_off,
+                     const uint8_t* t, const uint64_t* t_off,
+                     const int32_t* h0, const uint8_t* param_id,
+                     const bsw_params* params, int32_t n_params,
+                     bsw_result* out, bsw_diag* diag);
+
+/* Device-memory batch.  q, q_off, t, t_off, h0, param_id (nullable), out
+ * and diag (nullable) are device pointers; params is a host array.  The
+ * work is enqueued on `stream` (a hipStream_t; NULL = the context's own
+ * stream).  q_off[n] and t_off[n] are read on the device, so the sequence
+ * sizes need not be known on the host.  Per-pair checks (codes, lengths,
+ * h0, param_id) run on the device before any result is written; a bad
+ * pair makes the whole call write nothing.  With async = 0 the call waits
+ * for the stream and returns the final status; with async != 0 it returns
+ * after enqueueing and bsw_ctx_wait() returns the status later.  Between
+ * an asynchronous call and its wait the inputs must stay valid. */
+int bsw_extend_batch_device(bsw_ctx* ctx, int64_t n,
+                            const uint8_t* q, const uint64_t* q_off,
+                            const uint8_t* t, const uint64_t* t_off,
+                            const int32_t* h0, const uint8_t* param_id,
+                            const bsw_params* params, int32_t n_params,
+                            bsw_result* out, bsw_diag* diag,
+                            void* stream, int32_t async);
+
+/* Wait for the last asynchronous call on ctx and return its status
+ * (BSW_EINVAL with the first bad pair in bsw_last_error if a pair was
+ * rejected on the device). */
+int bsw_ctx_wait(bsw_ctx* ctx);
+
+/* Timing of the last completed call's device work, in milliseconds:
+ * [0] = whole pipeline (first to last kernel), [1] = prepare and bin,
+ * [2] = DP kernels, [3] = number of DP kernel launches.  Returns BSW_OK. */
+int bsw_ctx_last_timing(bsw_ctx* ctx, double out4[4]);
+
+/* Text of the calling thread's most recent error ("" if none). */
+const char* bsw_last_error(void);
+
+/* ABI version of the loaded library (BSW_ABI_VERSION). */
+int bsw_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

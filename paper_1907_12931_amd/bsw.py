@@ -1,0 +1,216 @@
+"""ctypes binding of libbsw.so (argument marshalling only).
+
+Every step of the extension runs in the library's HIP kernels; this module
+only converts NumPy arrays / torch tensors into the C ABI's pointers and
+sizes.  PyTorch is used for device memory and streams.  The library must
+have been built (``python -m paper_1907_12931_amd.build``); there is no
+other implementation to fall back to, so a missing or unloadable library
+raises ``BswError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbsw.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ETOOBIG, EBUSY, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+PATH_BATCHED, PATH_PLAIN = 0, 1
+STATUS_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
+                ETOOBIG: "ETOOBIG", EBUSY: "EBUSY", ETIMEOUT: "ETIMEOUT"}
+
+
+class BswError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("mat", ctypes.c_int8 * 25), ("pad_", ctypes.c_int8 * 3),
+                ("o_del", ctypes.c_int32), ("e_del", ctypes.c_int32),
+                ("o_ins", ctypes.c_int32), ("e_ins", ctypes.c_int32),
+                ("w", ctypes.c_int32), ("zdrop", ctypes.c_int32),
+                ("end_bonus", ctypes.c_int32)]
+
+
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("min_lane_bits", ctypes.c_int32),
+                ("force_mode", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t), ("tune_cache", ctypes.c_char_p)]
+
+
+RESULT_DTYPE = np.dtype([("score", "<i4"), ("qle", "<i4"), ("tle", "<i4"),
+                         ("gtle", "<i4"), ("gscore", "<i4"), ("max_off", "<i4")])
+DIAG_DTYPE = np.dtype([("rows", "<i4"), ("stop", "<i4"), ("cells", "<i8")])
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def lib():
+    """Load libbsw.so (raises BswError if it is not built).
+
+    torch is imported first when it is installed: its wheel carries its own
+    HIP runtime with the same soname as ROCm's, and loading ours first would
+    put two HIP runtimes in the process (torch then finds no GPU).  With
+    torch loaded, libbsw.so binds to torch's runtime and device pointers and
+    streams are shared."""
+    global _lib
+    if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise BswError(EDEVICE, f"{LIB_PATH} is not built; run "
+                           "python -m paper_1907_12931_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.bsw_abi_version.restype = ctypes.c_int
+        L.bsw_last_error.restype = ctypes.c_char_p
+        L.bsw_ctx_create.restype = ctypes.c_int
+        L.bsw_ctx_create.argtypes = [ctypes.POINTER(_VP), ctypes.POINTER(CtxOpts)]
+        L.bsw_ctx_destroy.restype = None
+        L.bsw_ctx_destroy.argtypes = [_VP]
+        L.bsw_extend_batch.restype = ctypes.c_int
+        L.bsw_extend_batch.argtypes = [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP,
+                                       _VP, ctypes.POINTER(Params), ctypes.c_int32,
+                                       _VP, _VP]
+        L.bsw_extend_batch_device.restype = ctypes.c_int
+        L.bsw_extend_batch_device.argtypes = [
+            _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP,
+            ctypes.POINTER(Params), ctypes.c_int32, _VP, _VP, _VP, ctypes.c_int32]
+        L.bsw_ctx_wait.restype = ctypes.c_int
+        L.bsw_ctx_wait.argtypes = [_VP]
+        L.bsw_ctx_last_timing.restype = ctypes.c_int
+        L.bsw_ctx_last_timing.argtypes = [_VP, ctypes.POINTER(ctypes.c_double)]
+        if L.bsw_abi_version() != 1:
+            raise BswError(EDEVICE, "libbsw.so ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().bsw_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise BswError(rc, last_error())
+
+
+def make_params(scorings):
+    arr = (Params * len(scorings))()
+    for i, sc in enumerate(scorings):
+        mat = np.asarray(sc["mat"], dtype=np.int64).reshape(25)
+        for k in range(25):
+            arr[i].mat[k] = int(mat[k])
+        for name in ("o_del", "e_del", "o_ins", "e_ins", "w", "zdrop", "end_bonus"):
+            setattr(arr[i], name, int(sc[name]))
+    return arr
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+class Context:
+    """A library context on one device (see ``bsw_ctx_create``)."""
+
+    def __init__(self, device=0, min_lane_bits=0, force_mode=0, path=PATH_BATCHED,
+                 hbm_budget=0, tune_cache=None):
+        o = CtxOpts(device, min_lane_bits, force_mode, path, hbm_budget,
+                    tune_cache.encode() if tune_cache else None)
+        h = _VP()
+        _check(lib().bsw_ctx_create(ctypes.byref(h), ctypes.byref(o)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bsw_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def extend(self, batch, with_diag=False):
+        """Host-memory batch (NumPy arrays, see ``synth``) -> results[, diag]."""
+        q = np.ascontiguousarray(batch["q"], dtype=np.uint8)
+        t = np.ascontiguousarray(batch["t"], dtype=np.uint8)
+        qo = np.ascontiguousarray(batch["q_off"], dtype=np.uint64)
+        to = np.ascontiguousarray(batch["t_off"], dtype=np.uint64)
+        h0 = np.ascontiguousarray(batch["h0"], dtype=np.int32)
+        pid = batch.get("param_id")
+        pid = None if pid is None else np.ascontiguousarray(pid, dtype=np.uint8)
+        n = len(h0)
+        params = make_params(batch["scorings"])
+        out = np.zeros(n, dtype=RESULT_DTYPE)
+        diag = np.zeros(n, dtype=DIAG_DTYPE) if with_diag else None
+        _check(lib().bsw_extend_batch(
+            self._h, n, _ptr(q), qo.ctypes.data, _ptr(t), to.ctypes.data,
+            _ptr(h0), _ptr(pid), params, len(params), _ptr(out), _ptr(diag)))
+        return (out, diag) if with_diag else out
+
+    def extend_device(self, dev, scorings, out, diag=None, stream=None, async_=False):
+        """Device batch: ``dev`` maps q, q_off, t, t_off, h0[, param_id] to
+        torch tensors on the GPU; ``out`` (and ``diag``) are torch tensors of
+        n*24 (n*16) bytes.  ``stream``: a torch.cuda.Stream or None."""
+        n = dev["h0"].numel()
+        params = make_params(scorings)
+        pid = dev.get("param_id")
+        s = stream.cuda_stream if stream is not None else None
+        _check(lib().bsw_extend_batch_device(
+            self._h, n, dev["q"].data_ptr(), dev["q_off"].data_ptr(),
+            dev["t"].data_ptr(), dev["t_off"].data_ptr(), dev["h0"].data_ptr(),
+            pid.data_ptr() if pid is not None else None, params, len(params),
+            out.data_ptr(), diag.data_ptr() if diag is not None else None, s,
+            1 if async_ else 0))
+
+    def wait(self):
+        _check(lib().bsw_ctx_wait(self._h))
+
+    def last_timing(self):
+        """(pipeline_ms, prep_bin_ms, dp_ms, dp_launches) of the last call."""
+        buf = (ctypes.c_double * 4)()
+        _check(lib().bsw_ctx_last_timing(self._h, buf))
+        return tuple(buf)
+
+
+def to_device(batch, device="cuda"):
+    """Copy a host batch's arrays into torch tensors on the GPU."""
+    import torch
+    dev = {}
+    for k in ("q", "q_off", "t", "t_off", "h0", "param_id"):
+        if k in batch and batch[k] is not None:
+            a = np.ascontiguousarray(batch[k])
+            if a.dtype == np.uint64:
+                a = a.view(np.int64)
+            dev[k] = torch.from_numpy(a).to(device)
+    return dev
+
+
+def alloc_outputs(n, device="cuda", with_diag=False):
+    import torch
+    out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=device)
+    diag = (torch.empty(n * DIAG_DTYPE.itemsize, dtype=torch.uint8, device=device)
+            if with_diag else None)
+    return out, diag
+
+
+def outputs_to_numpy(out, diag=None):
+    r = out.cpu().numpy().view(RESULT_DTYPE)
+    if diag is None:
+        return r
+    return r, diag.cpu().numpy().view(DIAG_DTYPE)

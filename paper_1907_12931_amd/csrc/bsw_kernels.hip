@@ -1,0 +1,546 @@
+// bsw_kernels.hip -- HIP kernels for banded Smith-Waterman seed extension on
+// gfx950 (MI355X).
+//
+// Pipeline of one batch (paper Sec. 5.3: sort tasks by length, then
+// convert to a vector-friendly layout, then run many pairs side by side):
+//   k_fill      zero the status block, histogram and tile counters
+//   k_prep      per pair: check lengths/h0/scoring id, pick the value width
+//               from the score bound (Sec. 5.4.1) and a kernel class from
+//               the query length, build a longest-first bin key, histogram
+//   k_codes     check that every sequence byte is a code 0..4
+//   k_scan      exclusive scan of the histogram -> bin starts, class ranges
+//   k_scatter   counting-sort scatter of pair descriptors into bins
+//   k_lane      the DP, one pair per lane (inter-task, Sec. 5.3), row
+//               buffer of H and E in LDS; results are written straight to
+//               the caller's position (no separate un-permute pass)
+//   k_long      the DP for queries longer than 256 (outside the paper's
+//               read lengths), one pair per wave, row buffer in HBM
+//
+// The cell update follows Sec. 5.1 Eq. (2) with the boundary of Eq. (3):
+// M = H(i-1,j-1) + S(t_i, q_j) taken only from a positive diagonal cell;
+// H = max(M, E, F); E(i+1,j) = max(E - e_del, M - o_del - e_del, 0);
+// F(i,j+1) = max(F - e_ins, M - o_ins - e_ins, 0).  Rows are target
+// positions, columns query positions; the one-row buffer holds H shifted
+// by one column (index j has H(i-1,j-1) when row i reaches it) and E.
+#include <hip/hip_runtime.h>
+
+#include "../../include/bsw.h"
+#include "bsw_internal.h"
+
+namespace bsw {
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+// Score of target code tb against query code qj: byte qj of the 8-byte
+// score row {hi, lo} of tb, sign-extended (v_perm picks the byte).
+__device__ __forceinline__ int score_of(uint32_t lo, uint32_t hi, uint32_t qj) {
+  return (int)(int8_t)(__builtin_amdgcn_perm(hi, lo, qj) & 0xffu);
+}
+
+// Band half-width after the end-bonus cap: a gap longer than
+// (qlen*A + bonus - o)/e + 1 can never pay for itself.
+__device__ __forceinline__ int band_cap(const KParams& P, int Lq) {
+  int w = P.w;
+  int num = Lq * P.amax + P.end_bonus - P.o_ins;
+  w = imin(w, num >= 0 ? num / P.e_ins + 1 : 1);
+  num = Lq * P.amax + P.end_bonus - P.o_del;
+  w = imin(w, num >= 0 ? num / P.e_del + 1 : 1);
+  return w;
+}
+
+// Row-buffer records: (H, E) of one column.
+template <int W> struct Rec;
+template <> struct Rec<W8> {
+  using T = uint16_t;
+  static __device__ __forceinline__ T pack(int h, int e) { return (T)(h | (e << 8)); }
+  static __device__ __forceinline__ int h(T r) { return r & 0xff; }
+  static __device__ __forceinline__ int e(T r) { return r >> 8; }
+  static __device__ __forceinline__ bool empty(T r) { return r == 0; }
+};
+template <> struct Rec<W16> {
+  using T = uint32_t;
+  static __device__ __forceinline__ T pack(int h, int e) { return (T)h | ((T)e << 16); }
+  static __device__ __forceinline__ int h(T r) { return (int)(r & 0xffffu); }
+  static __device__ __forceinline__ int e(T r) { return (int)(r >> 16); }
+  static __device__ __forceinline__ bool empty(T r) { return r == 0; }
+};
+template <> struct Rec<W32> {
+  using T = int2;
+  static __device__ __forceinline__ T pack(int h, int e) { return make_int2(h, e); }
+  static __device__ __forceinline__ int h(T r) { return r.x; }
+  static __device__ __forceinline__ int e(T r) { return r.y; }
+  static __device__ __forceinline__ bool empty(T r) { return (r.x | r.y) == 0; }
+};
+
+__device__ __forceinline__ uint32_t wave_first(uint32_t v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// ---------------------------------------------------------------------------
+// preparation kernels
+
+__global__ void k_fill(uint32_t* p, int64_t nwords) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+__global__ void k_prep(int64_t n, const uint64_t* __restrict__ q_off,
+                       const uint64_t* __restrict__ t_off,
+                       const int32_t* __restrict__ h0,
+                       const uint8_t* __restrict__ pid, int n_params,
+                       const KParams* __restrict__ kp, int min_bits,
+                       int force_mode, uint32_t* __restrict__ keys,
+                       uint32_t* __restrict__ hist, Status* st) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t qo = q_off[k], qe = q_off[k + 1];
+    const uint64_t to = t_off[k], te = t_off[k + 1];
+    const int p = pid ? pid[k] : 0;
+    const int hh = h0[k];
+    const bool ok = qe >= qo && te >= to && qe - qo <= BSW_MAX_LEN &&
+                    te - to <= BSW_MAX_LEN && hh >= 1 && hh <= BSW_MAX_H0 &&
+                    p < n_params;
+    if (!ok) {
+      atomicMax(&st->first_bad_inv, ~(unsigned long long)k);
+      atomicOr(&st->bad, 1u);
+      keys[k] = 0xffffffffu;
+      continue;
+    }
+    const int ql = (int)(qe - qo), tl = (int)(te - to);
+    // bound on every stored H and E of the pair (Sec. 5.4.1 precision)
+    const int64_t U = (int64_t)hh + (int64_t)kp[p].amax * (ql < tl ? ql : tl);
+    int wd = U <= 255 ? W8 : (U <= 65535 ? W16 : W32);
+    if (min_bits >= 16 && wd < W16) wd = W16;
+    if (min_bits >= 32) wd = W32;
+    (void)force_mode;
+    int cls, cap;
+    if (ql > LQ_CAP[NLQ - 1]) {
+      cls = CLS_LONG;
+      cap = BSW_MAX_LEN;
+      atomicMax(&st->long_max, (unsigned long long)ql);
+    } else {
+      int c = 0;
+      while (LQ_CAP[c] < ql) ++c;
+      cls = c * NWIDTH + wd;
+      cap = LQ_CAP[c];
+    }
+    // longest first inside a class: larger query, then larger target
+    int qq = (int)((int64_t)ql * 64 / (cap + 1));
+    int tq = tl >> 4;
+    qq = qq > 63 ? 63 : qq;
+    tq = tq > 63 ? 63 : tq;
+    const uint32_t key = ((uint32_t)cls << KEY_SUB_BITS) |
+                         ((uint32_t)(63 - qq) << 6) | (uint32_t)(63 - tq);
+    keys[k] = key;
+    atomicAdd(&hist[key], 1u);
+  }
+}
+
+// Every byte of q[off[0] .. off[n]) must be a code 0..4; a bad byte names
+// the pair that holds it (binary search over the offsets).
+__global__ void k_codes(const uint8_t* __restrict__ s,
+                        const uint64_t* __restrict__ off, int64_t n,
+                        Status* st) {
+  const uint64_t lo = off[0], hi = off[n];
+  if (hi <= lo) return;
+  const uint64_t len = hi - lo;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  // 4 bytes per step; the leading bytes up to a 4-byte boundary and the
+  // tail are checked one by one
+  const uint64_t head = (4 - ((uintptr_t)(s + lo) & 3)) & 3;
+  const uint64_t h = head < len ? head : len;
+  const uint64_t nw = (len - h) >> 2;
+  const uint32_t* w = (const uint32_t*)(s + lo + h);
+  const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t badpos = ~0ull;
+  for (uint64_t i = tid; i < nw; i += stride) {
+    const uint32_t v = w[i];
+    // a byte is > 4 iff (byte + 0x7b) has bit 7 set, for bytes <= 0x84;
+    // bytes >= 0x80 are caught by their own top bit
+    const uint32_t t = ((v & 0x7f7f7f7fu) + 0x7b7b7b7bu) | v;
+    if (t & 0x80808080u) {
+      for (int b = 0; b < 4; ++b)
+        if (((v >> (8 * b)) & 0xffu) > 4) {
+          badpos = lo + h + i * 4 + b;
+          break;
+        }
+    }
+  }
+  if (tid < h && s[lo + tid] > 4) badpos = lo + tid;
+  const uint64_t tail = h + nw * 4;
+  if (tid < len - tail && s[lo + tail + tid] > 4) badpos = lo + tail + tid;
+  if (badpos != ~0ull) {
+    int64_t a = 0, b = n - 1;  // largest k with off[k] <= badpos
+    while (a < b) {
+      const int64_t m = (a + b + 1) >> 1;
+      if (off[m] <= badpos) a = m; else b = m - 1;
+    }
+    // skip empty pairs that share the offset
+    while (a + 1 < n && off[a + 1] <= badpos) ++a;
+    atomicMax(&st->first_bad_inv, ~(unsigned long long)a);
+    atomicOr(&st->bad, 1u);
+  }
+}
+
+// One block: exclusive scan of hist into cursor, class ranges.
+__global__ void __launch_bounds__(1024)
+k_scan(const uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor,
+       int64_t* __restrict__ cls_range) {
+  __shared__ uint32_t part[1024];
+  constexpr int PER = (NBINS + 1023) / 1024;
+  const int tid = threadIdx.x;
+  const int b0 = tid * PER;
+  uint32_t s = 0;
+  for (int i = 0; i < PER; ++i)
+    if (b0 + i < NBINS) s += hist[b0 + i];
+  part[tid] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint32_t v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = tid ? part[tid - 1] : 0;
+  for (int i = 0; i < PER; ++i) {
+    const int b = b0 + i;
+    if (b < NBINS) {
+      cursor[b] = run;
+      if ((b & ((1 << KEY_SUB_BITS) - 1)) == 0) cls_range[2 * (b >> KEY_SUB_BITS)] = run;
+      run += hist[b];
+    }
+  }
+  __syncthreads();
+  if (tid < NCLS) {
+    // count of class tid = start of the next class - own start
+    const int64_t beg = cls_range[2 * tid];
+    const int64_t end = tid + 1 < NCLS ? cls_range[2 * (tid + 1)] : (int64_t)part[1023];
+    cls_range[2 * tid + 1] = end - beg;
+  }
+}
+
+__global__ void k_scatter(int64_t n, const uint64_t* __restrict__ q_off,
+                          const uint64_t* __restrict__ t_off,
+                          const int32_t* __restrict__ h0,
+                          const uint8_t* __restrict__ pid,
+                          const uint32_t* __restrict__ keys,
+                          uint32_t* __restrict__ cursor,
+                          PairDesc* __restrict__ desc, const Status* st) {
+  if (st->bad) return;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t key = keys[k];
+    const uint32_t pos = atomicAdd(&cursor[key], 1u);
+    PairDesc d;
+    d.qo = q_off[k];
+    d.to = t_off[k];
+    d.ql = (uint16_t)(q_off[k + 1] - d.qo);
+    d.tl = (uint16_t)(t_off[k + 1] - d.to);
+    d.h0 = h0[k];
+    d.idx = (uint32_t)k;
+    d.pid = pid ? pid[k] : 0;
+    d.cls = (uint8_t)(key >> KEY_SUB_BITS);
+    d.pad_[0] = d.pad_[1] = 0;
+    desc[pos] = d;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the DP for one pair in one lane; the row buffer entry of column j lives at
+// hb[j * S] and the query code at qb[j * S] (S = 64 in LDS, so that the 64
+// lanes of a wave hit distinct banks; S = 1 for a private buffer)
+
+template <int W, int S>
+__device__ __forceinline__ void extend_pair(const PairDesc& pd, const KParams& P,
+                                            const uint8_t* __restrict__ q,
+                                            const uint8_t* __restrict__ t,
+                                            typename Rec<W>::T* hb, uint8_t* qb,
+                                            bsw_result* __restrict__ out,
+                                            bsw_diag* __restrict__ diag) {
+  using R = Rec<W>;
+  const int Lq = pd.ql, Lt = pd.tl, h0 = pd.h0;
+  const int oD = P.o_del, eD = P.e_del, eI = P.e_ins;
+  const int oeD = P.oe_del, oeI = P.oe_ins, oI = P.o_ins;
+  const int zd = P.zdrop;
+  const int wb = band_cap(P, Lq);
+  uint32_t pl[5], ph[5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    pl[a] = P.prow[a][0];
+    ph[a] = P.prow[a][1];
+  }
+
+  // first row of Eq. (3): H(-1, j-1) = max(0, h0 - o_ins - e_ins*j), E = 0
+  hb[0] = R::pack(h0, 0);
+  for (int j = 1; j <= Lq; ++j) hb[j * S] = R::pack(imax(0, h0 - oI - eI * j), 0);
+  const uint8_t* qs = q + pd.qo;
+  for (int j = 0; j < Lq; ++j) qb[j * S] = qs[j];
+
+  int best = h0, bi = -1, bj = -1, gbest = -1, gi = -1, moff = 0;
+  int beg = 0, end = Lq, rows = 0, stop = 0;
+  int64_t cells = 0;
+  const uint8_t* ts = t + pd.to;
+  for (int i = 0; i < Lt; ++i) {
+    ++rows;
+    // band (Sec. 5.1 (a))
+    beg = imax(beg, i - wb);
+    end = imin(imin(end, i + wb + 1), Lq);
+    if (end > beg) cells += end - beg;
+    // score row of this target base
+    const int tb = ts[i];
+    uint32_t lo = pl[0], hi = ph[0];
+#pragma unroll
+    for (int a = 1; a < 5; ++a) {
+      lo = tb == a ? pl[a] : lo;
+      hi = tb == a ? ph[a] : hi;
+    }
+    // first column of Eq. (3) while the band starts at column 0
+    int hl = beg == 0 ? imax(0, h0 - oD - eD * (i + 1)) : 0;
+    int f = 0, m = 0, mj = -1;
+    for (int j = beg; j < end; ++j) {
+      const typename R::T r = hb[j * S];
+      const int d = R::h(r), e = R::e(r);
+      const int s = score_of(lo, hi, qb[j * S]);
+      const int M = d > 0 ? d + s : 0;
+      const int h = imax(imax(M, e), f);
+      const int en = imax(imax(e - eD, M - oeD), 0);
+      hb[j * S] = R::pack(hl, en);
+      hl = h;
+      mj = h >= m ? j : mj;
+      m = imax(m, h);
+      f = imax(imax(f - eI, M - oeI), 0);
+    }
+    hb[end * S] = R::pack(hl, 0);
+    // best score touching the end of the query (Sec. 5.4 (b))
+    if (imax(beg, end) == Lq) {
+      gi = hl >= gbest ? i : gi;
+      gbest = imax(gbest, hl);
+    }
+    // all-zero row (Sec. 5.1 (b))
+    if (m == 0) {
+      stop = 1;
+      break;
+    }
+    if (m > best) {
+      best = m;
+      bi = i;
+      bj = mj;
+      moff = imax(moff, mj > i ? mj - i : i - mj);
+    } else if (zd > 0) {
+      // drop from the best, net of the gap the drift between the two
+      // cells would cost (Sec. 5.1 (b))
+      const int drift = (i - bi) - (mj - bj);
+      const int drop = best - m - (drift > 0 ? drift * eD : -drift * eI);
+      if (drop > zd) {
+        stop = 2;
+        break;
+      }
+    }
+    // shrink the band by its empty ends (Sec. 5.1 (c))
+    while (beg < end && R::empty(hb[beg * S])) ++beg;
+    int k = end;
+    while (k >= beg && R::empty(hb[k * S])) --k;
+    end = imin(k + 2, Lq);
+  }
+  bsw_result res;
+  res.score = best;
+  res.qle = bj + 1;
+  res.tle = bi + 1;
+  res.gtle = gi + 1;
+  res.gscore = gbest;
+  res.max_off = moff;
+  out[pd.idx] = res;
+  if (diag) {
+    bsw_diag dg;
+    dg.rows = rows;
+    dg.stop = stop;
+    dg.cells = cells;
+    diag[pd.idx] = dg;
+  }
+}
+
+// Lane mode: one wave runs a tile of 64 pairs of one class.  PERSIST: waves
+// pull tiles from a counter until the class is done (tiles are in
+// longest-first order); otherwise wave w of the grid runs tile w.
+template <int W, int LQCAP, bool PERSIST>
+__global__ void __launch_bounds__(256)
+k_lane(const PairDesc* __restrict__ desc, const int64_t* __restrict__ cls_range,
+       int cls, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
+       const KParams* __restrict__ kp, bsw_result* __restrict__ out,
+       bsw_diag* __restrict__ diag, uint32_t* tile_ctr, const Status* st) {
+  if (st->bad) return;
+  using T = typename Rec<W>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr size_t HB_BYTES = (size_t)(LQCAP + 1) * 64 * sizeof(T);
+  constexpr size_t PER_WAVE = HB_BYTES + (size_t)LQCAP * 64;
+  T* hb = (T*)(smem + wv * PER_WAVE) + lane;
+  uint8_t* qb = smem + wv * PER_WAVE + HB_BYTES + lane;
+  const int64_t begin = cls_range[2 * cls], count = cls_range[2 * cls + 1];
+  const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
+  uint32_t tile = blockIdx.x * (blockDim.x >> 6) + wv;
+  for (;;) {
+    if (PERSIST) {
+      uint32_t v = 0;
+      if (lane == 0) v = atomicAdd(tile_ctr, 1u);
+      tile = wave_first(__shfl(v, 0));
+    }
+    if (tile >= ntiles) break;
+    const int64_t k = (int64_t)tile * 64 + lane;
+    if (k < count) {
+      const PairDesc pd = desc[begin + k];
+      extend_pair<W, 64>(pd, kp[pd.pid], q, t, hb, qb, out, diag);
+    }
+    if (!PERSIST) break;
+  }
+}
+
+// Queries longer than 256: one pair per wave, lane 0 runs it with a
+// 32-bit row buffer in HBM (slot per wave); waves pull pairs from a counter.
+__global__ void __launch_bounds__(64)
+k_long(const PairDesc* __restrict__ desc, const int64_t* __restrict__ cls_range,
+       const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
+       const KParams* __restrict__ kp, bsw_result* __restrict__ out,
+       bsw_diag* __restrict__ diag, uint32_t* ctr, int2* __restrict__ gbuf,
+       uint8_t* __restrict__ gq, const Status* st) {
+  if (st->bad) return;
+  const int64_t begin = cls_range[2 * CLS_LONG], count = cls_range[2 * CLS_LONG + 1];
+  int2* hb = gbuf + (size_t)blockIdx.x * LONG_SLOT_COLS;
+  uint8_t* qb = gq + (size_t)blockIdx.x * LONG_SLOT_COLS;
+  for (;;) {
+    uint32_t v = 0;
+    if (threadIdx.x == 0) v = atomicAdd(ctr, 1u);
+    const uint32_t k = wave_first(__shfl(v, 0));
+    if (k >= count) break;
+    if (threadIdx.x == 0) {
+      const PairDesc pd = desc[begin + k];
+      extend_pair<W32, 1>(pd, kp[pd.pid], q, t, hb, qb, out, diag);
+    }
+  }
+}
+
+}  // namespace bsw
+
+// ---------------------------------------------------------------------------
+// host-side launchers (called by the runtime in bsw_host.cpp)
+
+namespace bsw {
+
+template <int W, int LQ>
+constexpr size_t lane_wave_bytes() {
+  return (size_t)(LQ + 1) * 64 * sizeof(typename Rec<W>::T) + (size_t)LQ * 64;
+}
+
+size_t lane_lds_per_wave(int cls) {
+  const int w = cls % NWIDTH, c = cls / NWIDTH;
+  const size_t rec = w == W8 ? 2 : (w == W16 ? 4 : 8);
+  return (size_t)(LQ_CAP[c] + 1) * 64 * rec + (size_t)LQ_CAP[c] * 64;
+}
+
+// waves per workgroup: as many as fit in 64 KiB of LDS (1..4)
+int lane_waves_per_block(int cls) {
+  const size_t b = lane_lds_per_wave(cls);
+  int w = (int)(65536 / b);
+  return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
+typedef void (*LaneFn)(const PairDesc*, const int64_t*, int, const uint8_t*,
+                       const uint8_t*, const KParams*, bsw_result*, bsw_diag*,
+                       uint32_t*, const Status*);
+
+template <int W, int C, bool P>
+static LaneFn lane_fn_one() {
+  return k_lane<W, LQ_CAP[C], P>;
+}
+
+static LaneFn lane_fn(int cls, bool persist) {
+  static LaneFn tab[2][CLS_LANE_END] = {
+      {lane_fn_one<W8, 0, false>(), lane_fn_one<W16, 0, false>(), lane_fn_one<W32, 0, false>(),
+       lane_fn_one<W8, 1, false>(), lane_fn_one<W16, 1, false>(), lane_fn_one<W32, 1, false>(),
+       lane_fn_one<W8, 2, false>(), lane_fn_one<W16, 2, false>(), lane_fn_one<W32, 2, false>(),
+       lane_fn_one<W8, 3, false>(), lane_fn_one<W16, 3, false>(), lane_fn_one<W32, 3, false>()},
+      {lane_fn_one<W8, 0, true>(), lane_fn_one<W16, 0, true>(), lane_fn_one<W32, 0, true>(),
+       lane_fn_one<W8, 1, true>(), lane_fn_one<W16, 1, true>(), lane_fn_one<W32, 1, true>(),
+       lane_fn_one<W8, 2, true>(), lane_fn_one<W16, 2, true>(), lane_fn_one<W32, 2, true>(),
+       lane_fn_one<W8, 3, true>(), lane_fn_one<W16, 3, true>(), lane_fn_one<W32, 3, true>()}};
+  return tab[persist ? 1 : 0][cls];
+}
+
+hipError_t lane_setup(int cls, bool persist) {
+  const size_t lds = lane_lds_per_wave(cls) * lane_waves_per_block(cls);
+  return hipFuncSetAttribute((const void*)lane_fn(cls, persist),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// resident workgroups per CU for a lane-mode class
+int lane_blocks_per_cu(int cls, bool persist) {
+  int nb = 0;
+  const int wpb = lane_waves_per_block(cls);
+  const size_t lds = lane_lds_per_wave(cls) * wpb;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)lane_fn(cls, persist),
+                                                   wpb * 64, lds) != hipSuccess)
+    return 1;
+  return nb < 1 ? 1 : nb;
+}
+
+void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s) {
+  int64_t blocks = (nwords + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, nwords);
+}
+
+void launch_prep(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
+                 const int32_t* h0, const uint8_t* pid, int n_params,
+                 const KParams* kp, int min_bits, int force_mode, uint32_t* keys,
+                 uint32_t* hist, Status* st, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)blocks), dim3(256), 0, s, n, q_off,
+                     t_off, h0, pid, n_params, kp, min_bits, force_mode, keys, hist, st);
+}
+
+void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_codes, dim3(4096), dim3(256), 0, s, seq, off, n, st);
+}
+
+void launch_scan(const uint32_t* hist, uint32_t* cursor, int64_t* cls_range,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, cursor, cls_range);
+}
+
+void launch_scatter(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
+                    const int32_t* h0, const uint8_t* pid, const uint32_t* keys,
+                    uint32_t* cursor, PairDesc* desc, const Status* st,
+                    hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, n, q_off,
+                     t_off, h0, pid, keys, cursor, desc, st);
+}
+
+void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
+                 const int64_t* cls_range, const uint8_t* q, const uint8_t* t,
+                 const KParams* kp, bsw_result* out, bsw_diag* diag,
+                 uint32_t* tile_ctr, const Status* st, hipStream_t s) {
+  const int wpb = lane_waves_per_block(cls);
+  const size_t lds = lane_lds_per_wave(cls) * wpb;
+  hipLaunchKernelGGL(lane_fn(cls, persist), dim3(blocks), dim3(wpb * 64), lds, s,
+                     desc, cls_range, cls, q, t, kp, out, diag, tile_ctr, st);
+}
+
+void launch_long(const PairDesc* desc, const int64_t* cls_range, const uint8_t* q,
+                 const uint8_t* t, const KParams* kp, bsw_result* out,
+                 bsw_diag* diag, uint32_t* ctr, int2* gbuf, uint8_t* gq,
+                 const Status* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_long, dim3(LONG_SLOTS), dim3(64), 0, s, desc, cls_range, q, t,
+                     kp, out, diag, ctr, gbuf, gq, st);
+}
+
+}  // namespace bsw

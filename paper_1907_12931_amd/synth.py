@@ -125,6 +125,23 @@ def _sprinkle_n(rng, seq, p):
     return seq
 
 
+def _chunk_rngs(seed, nchunks):
+    """Independent generators for the chunks of a workload, derived from the
+    workload seed (so chunks can be drawn in any order or in parallel)."""
+    return [np.random.Generator(np.random.PCG64(s))
+            for s in np.random.SeedSequence(seed).spawn(nchunks)]
+
+
+def _map_chunks(fn, args, workers):
+    if workers <= 1 or len(args) <= 1:
+        return [fn(*a) for a in args]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=min(workers, len(args)),
+                                mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(fn, *zip(*args)))
+
+
 def _assemble(chunks, scorings):
     qs, ts, qls, tls, h0s, pids = zip(*chunks)
     ql = np.concatenate(qls)
@@ -163,24 +180,26 @@ def plain_small(n=1000, seed=0):
     return _assemble([(q, t, ql, tl, h0, None)], [BWA_DEFAULT])
 
 
-def read_scale(n=1_000_000, seed=1, chunk=250_000):
+def _read_scale_chunk(rng, m):
+    qlen = rng.integers(1, 151, size=m).astype(np.int64)
+    extra = rng.integers(0, 201, size=m).astype(np.int64)
+    p_sub = rng.uniform(0.01, 0.05, size=m)
+    p_ind = rng.uniform(0.001, 0.01, size=m)
+    # flank long enough that truncation to qlen + extra always applies
+    flank = extra + 60
+    q, t, ql, tl, h0 = _read_pairs(rng, qlen, p_sub, p_ind, 2.0, flank,
+                                   qlen + extra, 0.01, (19, 50))
+    return (q, t, ql, tl, h0, None)
+
+
+def read_scale(n=1_000_000, seed=1, chunk=125_000, workers=1):
     """Extension remainders of simulated 151 bp reads: qlen uniform in
     [1, 150]; per pair substitutions 1-5% and indels 0.1-1%; target = mutated
     query + flank, total qlen + U[0, 200] (2w); 1% of bases N."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    chunks = []
-    for s in range(0, n, chunk):
-        m = min(chunk, n - s)
-        qlen = rng.integers(1, 151, size=m).astype(np.int64)
-        extra = rng.integers(0, 201, size=m).astype(np.int64)
-        p_sub = rng.uniform(0.01, 0.05, size=m)
-        p_ind = rng.uniform(0.001, 0.01, size=m)
-        # flank long enough that truncation to qlen + extra always applies
-        flank = extra + 60
-        q, t, ql, tl, h0 = _read_pairs(rng, qlen, p_sub, p_ind, 2.0, flank,
-                                       qlen + extra, 0.01, (19, 50))
-        chunks.append((q, t, ql, tl, h0, None))
-    return _assemble(chunks, [BWA_DEFAULT])
+    sizes = [min(chunk, n - s) for s in range(0, n, chunk)] or [0]
+    rngs = _chunk_rngs(seed, len(sizes))
+    return _assemble(_map_chunks(_read_scale_chunk, list(zip(rngs, sizes)), workers),
+                     [BWA_DEFAULT])
 
 
 def _zdrop_pairs(rng, m):
@@ -210,41 +229,41 @@ def _zdrop_pairs(rng, m):
     return q, t, qlen, tlen, h0
 
 
-def batched_mix(n=4_000_000, seed=2, chunk=250_000, zdrop_frac=0.20):
+def _batched_mix_chunk(rng, m, zdrop_frac):
+    nz = int(round(m * zdrop_frac))
+    nr = m - nz
+    src = rng.choice(np.array([100, 150, 250]), size=nr)
+    qlen = (rng.random(nr) * src).astype(np.int64) + 1
+    d = rng.uniform(0.0, 0.15, size=nr)
+    extra = rng.integers(0, 201, size=nr).astype(np.int64)
+    q1, t1, ql1, tl1, h01 = _read_pairs(
+        rng, qlen, 0.9 * d, 0.1 * d, 2.0, extra + 60, qlen + extra, 0.0,
+        (19, 50))
+    q2, t2, ql2, tl2, h02 = _zdrop_pairs(rng, nz)
+    # interleave the two groups in random order
+    order = rng.permutation(m)
+    ql = np.concatenate([ql1, ql2])
+    tl = np.concatenate([tl1, tl2])
+    qo = _offsets(ql).astype(np.int64)
+    to = _offsets(tl).astype(np.int64)
+    qi = _gather_ranges(qo, order, ql[order])
+    ti = _gather_ranges(to, order, tl[order])
+    h0 = np.concatenate([h01, h02])[order]
+    return (np.concatenate([q1, q2])[qi], np.concatenate([t1, t2])[ti],
+            ql[order], tl[order], h0, None)
+
+
+def batched_mix(n=4_000_000, seed=2, chunk=125_000, zdrop_frac=0.20, workers=1):
     """Uneven pairs from 100/150/250 bp read sources (one third each):
     qlen uniform in [1, L]; divergence d uniform in [0, 15%], 0.9 d as
     substitutions and 0.1 d as indels (geometric, mean 2); target = mutated
     query + flank, total at most qlen + 200.  A fraction zdrop_frac of the
     pairs are built to end by z-drop (see _zdrop_pairs); positions of those
     pairs in the batch are random."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    chunks = []
-    for s in range(0, n, chunk):
-        m = min(chunk, n - s)
-        nz = int(round(m * zdrop_frac))
-        nr = m - nz
-        src = rng.choice(np.array([100, 150, 250]), size=nr)
-        qlen = (rng.random(nr) * src).astype(np.int64) + 1
-        d = rng.uniform(0.0, 0.15, size=nr)
-        extra = rng.integers(0, 201, size=nr).astype(np.int64)
-        q1, t1, ql1, tl1, h01 = _read_pairs(
-            rng, qlen, 0.9 * d, 0.1 * d, 2.0, extra + 60, qlen + extra, 0.0,
-            (19, 50))
-        q2, t2, ql2, tl2, h02 = _zdrop_pairs(rng, nz)
-        # interleave the two groups in random order
-        order = rng.permutation(m)
-        ql = np.concatenate([ql1, ql2])
-        tl = np.concatenate([tl1, tl2])
-        qa = np.concatenate([q1, q2])
-        ta = np.concatenate([t1, t2])
-        qo = _offsets(ql).astype(np.int64)
-        to = _offsets(tl).astype(np.int64)
-        qlo, tlo = ql[order], tl[order]
-        qi = _gather_ranges(qo, order, qlo)
-        ti = _gather_ranges(to, order, tlo)
-        h0 = np.concatenate([h01, h02])[order]
-        chunks.append((qa[qi], ta[ti], qlo, tlo, h0, None))
-    return _assemble(chunks, [BWA_DEFAULT])
+    sizes = [min(chunk, n - s) for s in range(0, n, chunk)] or [0]
+    rngs = _chunk_rngs(seed, len(sizes))
+    args = [(r, m, zdrop_frac) for r, m in zip(rngs, sizes)]
+    return _assemble(_map_chunks(_batched_mix_chunk, args, workers), [BWA_DEFAULT])
 
 
 def _gather_ranges(off, order, lens):
@@ -255,33 +274,35 @@ def _gather_ranges(off, order, lens):
     return starts[pid] + np.arange(int(lens.sum()), dtype=np.int64) - base[:-1][pid]
 
 
-def wide_band(n=500_000, seed=4, chunk=100_000):
+def _wide_band_chunk(rng, m):
+    qlen = np.full(m, 250, dtype=np.int64)
+    rich = rng.random(m) < 0.10
+    p_sub = np.where(rich, 0.02, rng.uniform(0.0, 0.05, size=m))
+    p_ind = np.where(rich, 0.02, rng.uniform(0.001, 0.01, size=m))
+    q = _random_bases(rng, int(qlen.sum()))
+    # indel-rich pairs: geometric mean 25 (runs mostly within 1..50)
+    mut_n, ml_n = _mutate(rng, q, qlen, np.where(rich, 0, p_sub),
+                          np.where(rich, 0, p_ind), 2.0)
+    mut_r, ml_r = _mutate(rng, q, qlen, np.where(rich, p_sub, 0),
+                          np.where(rich, p_ind, 0), 25.0)
+    mut, ml = _pick(rich, mut_n, ml_n, mut_r, ml_r)
+    flank = rng.integers(0, 501, size=m).astype(np.int64)
+    fl = _random_bases(rng, int(flank.sum()))
+    t, tlen = _join(mut, ml, fl, flank, np.full(m, 750, dtype=np.int64))
+    h0 = rng.integers(19, 51, size=m)
+    pid = (rng.random(m) < 0.5).astype(np.uint8)
+    return (q, t, qlen, tlen, h0, pid)
+
+
+def wide_band(n=500_000, seed=4, chunk=50_000, workers=1):
     """250 bp queries against targets of up to 750 bp, w 500, z-drop 400,
     two scoring sets (match 1 / mismatch -4 / gap 6+k; match 2 / mismatch
     -3 / gap 5+2k) chosen per pair with probability 1/2; 10% of pairs are
     indel-rich (runs of 1-50 bp, about one per 50 bp)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    chunks = []
-    for s in range(0, n, chunk):
-        m = min(chunk, n - s)
-        qlen = np.full(m, 250, dtype=np.int64)
-        rich = rng.random(m) < 0.10
-        p_sub = np.where(rich, 0.02, rng.uniform(0.0, 0.05, size=m))
-        p_ind = np.where(rich, 0.02, rng.uniform(0.001, 0.01, size=m))
-        q = _random_bases(rng, int(qlen.sum()))
-        # rich pairs: geometric mean 25 (runs mostly within 1..50)
-        mut_n, ml_n = _mutate(rng, q, qlen, np.where(rich, 0, p_sub),
-                              np.where(rich, 0, p_ind), 2.0)
-        mut_r, ml_r = _mutate(rng, q, qlen, np.where(rich, p_sub, 0),
-                              np.where(rich, p_ind, 0), 25.0)
-        mut, ml = _pick(rich, mut_n, ml_n, mut_r, ml_r)
-        flank = rng.integers(0, 501, size=m).astype(np.int64)
-        fl = _random_bases(rng, int(flank.sum()))
-        t, tlen = _join(mut, ml, fl, flank, np.full(m, 750, dtype=np.int64))
-        h0 = rng.integers(19, 51, size=m)
-        pid = (rng.random(m) < 0.5).astype(np.uint8)
-        chunks.append((q, t, qlen, tlen, h0, pid))
-    return _assemble(chunks, [WIDE_A, WIDE_B])
+    sizes = [min(chunk, n - s) for s in range(0, n, chunk)] or [0]
+    rngs = _chunk_rngs(seed, len(sizes))
+    return _assemble(_map_chunks(_wide_band_chunk, list(zip(rngs, sizes)), workers),
+                     [WIDE_A, WIDE_B])
 
 
 def _pick(mask, a, la, b, lb):

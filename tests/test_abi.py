@@ -1,0 +1,47 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/bsw.h declares, and reports the absence of a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "bsw.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bsw_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("bsw_ctx_create", "bsw_ctx_destroy", "bsw_extend_batch",
+                 "bsw_extend_batch_device", "bsw_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1907_12931_amd import bsw
+    lib = bsw.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.bsw_abi_version() == 1
+
+
+def test_no_gpu_gives_edevice():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_1907_12931_amd import bsw
+    with pytest.raises(bsw.BswError) as ei:
+        bsw.Context()
+    assert ei.value.code == bsw.EDEVICE
+
+
+def test_params_layout():
+    from paper_1907_12931_amd import bsw
+    import oracle
+    assert ctypes.sizeof(bsw.Params) == 56 == ctypes.sizeof(oracle.Params)
+    assert bsw.RESULT_DTYPE.itemsize == 24 and bsw.DIAG_DTYPE.itemsize == 16
