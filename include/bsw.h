@@ -152,6 +152,18 @@ int bsw_ctx_wait(bsw_ctx* ctx);
  * [2] = DP kernels, [3] = number of DP kernel launches.  Returns BSW_OK. */
 int bsw_ctx_last_timing(bsw_ctx* ctx, double out4[4]);
 
+/* Per-launch record of the last completed call's DP kernels: for launch k,
+ * cls[k] = kernel class (see bsw_class_name), cells[k] = band cells the
+ * launch settled, ms[k] = its device time from HIP events on the launch
+ * stream.  Any output pointer may be NULL; at most max entries are
+ * written.  Returns the number of launches (may exceed max). */
+int bsw_ctx_last_kernels(bsw_ctx* ctx, int32_t* cls, int64_t* cells, double* ms,
+                         int32_t max);
+
+/* Name of a kernel class ("lane8_q256" = one pair per lane, 8-bit row
+ * buffer, queries up to 256; "rerun16" = 16-bit rerun of 8-bit overflows). */
+const char* bsw_class_name(int32_t cls);
+
 /* Text of the calling thread's most recent error ("" if none). */
 const char* bsw_last_error(void);
 

@@ -85,6 +85,10 @@ def lib():
             ctypes.POINTER(Params), ctypes.c_int32, _VP, _VP, _VP, ctypes.c_int32]
         L.bsw_ctx_wait.restype = ctypes.c_int
         L.bsw_ctx_wait.argtypes = [_VP]
+        L.bsw_ctx_last_kernels.restype = ctypes.c_int
+        L.bsw_ctx_last_kernels.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_int32]
+        L.bsw_class_name.restype = ctypes.c_char_p
+        L.bsw_class_name.argtypes = [ctypes.c_int32]
         L.bsw_ctx_last_timing.restype = ctypes.c_int
         L.bsw_ctx_last_timing.argtypes = [_VP, ctypes.POINTER(ctypes.c_double)]
         if L.bsw_abi_version() != 1:
@@ -180,6 +184,18 @@ class Context:
 
     def wait(self):
         _check(lib().bsw_ctx_wait(self._h))
+
+    def last_kernels(self):
+        """Per DP launch of the last call: list of (class name, cells, ms)."""
+        cls = np.zeros(32, dtype=np.int32)
+        cells = np.zeros(32, dtype=np.int64)
+        ms = np.zeros(32, dtype=np.float64)
+        n = lib().bsw_ctx_last_kernels(self._h, cls.ctypes.data, cells.ctypes.data,
+                                       ms.ctypes.data, 32)
+        if n < 0:
+            _check(n)
+        return [(lib().bsw_class_name(int(cls[k])).decode(), int(cells[k]), float(ms[k]))
+                for k in range(min(n, 32))]
 
     def last_timing(self):
         """(pipeline_ms, prep_bin_ms, dp_ms, dp_launches) of the last call."""

@@ -23,7 +23,9 @@ namespace bsw {
 size_t lane_lds_per_wave(int cls);
 int lane_waves_per_block(int cls);
 hipError_t lane_setup(int cls, bool persist);
-int lane_blocks_per_cu(int cls, bool persist);
+int lane_blocks_per_cu(int cls, bool persist, size_t lds);
+int lane8_ring_chunks(int cls, int wmax);
+size_t lane8_qtile_words(int cls);
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
 void launch_prep(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
                  const int32_t* h0, const uint8_t* pid, int n_params,
@@ -31,20 +33,22 @@ void launch_prep(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
                  uint32_t* hist, Status* st, hipStream_t s);
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
                   hipStream_t s);
-void launch_scan(const uint32_t* hist, uint32_t* cursor, int64_t* cls_range,
+void launch_scan(const uint32_t* hist, uint32_t* cursor, long long* cls_range,
                  hipStream_t s);
 void launch_scatter(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
                     const int32_t* h0, const uint8_t* pid, const uint32_t* keys,
                     uint32_t* cursor, PairDesc* desc, const Status* st,
                     hipStream_t s);
 void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
-                 const int64_t* cls_range, const uint8_t* q, const uint8_t* t,
+                 const long long* range, const uint8_t* q, const uint8_t* t,
                  const KParams* kp, bsw_result* out, bsw_diag* diag,
-                 uint32_t* tile_ctr, const Status* st, hipStream_t s);
-void launch_long(const PairDesc* desc, const int64_t* cls_range, const uint8_t* q,
+                 uint32_t* tile_ctr, const Status* st, uint32_t* qtiles,
+                 PairDesc* ovf, Status* stw, int ring, bool sym,
+                 unsigned long long* cls_cells, hipStream_t s);
+void launch_long(const PairDesc* desc, const long long* range, const uint8_t* q,
                  const uint8_t* t, const KParams* kp, bsw_result* out,
                  bsw_diag* diag, uint32_t* ctr, int2* gbuf, uint8_t* gq,
-                 const Status* st, hipStream_t s);
+                 const Status* st, unsigned long long* cls_cells, hipStream_t s);
 }  // namespace bsw
 
 using namespace bsw;
@@ -99,10 +103,10 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up for n pairs.
 struct Layout {
-  size_t keys, desc, hist, cursor, cls_range, status, ctr, zero_beg, zero_end, total;
+  size_t keys, desc, ovf, hist, cursor, cls_range, status, ctr, zero_beg, zero_end, total;
 };
 
-constexpr int NCTR = NCLS + 1;
+constexpr int NCTR = NCLS + 2;  // one tile counter per class, the rerun, spare
 
 Layout layout_for(int64_t n) {
   Layout L;
@@ -123,6 +127,8 @@ Layout layout_for(int64_t n) {
   L.keys = o;
   o = align_up(o + (size_t)n * 4, 256);
   L.desc = o;
+  o = align_up(o + (size_t)n * sizeof(PairDesc), 256);
+  L.ovf = o;
   o = align_up(o + (size_t)n * sizeof(PairDesc), 256);
   L.total = o;
   return L;
@@ -178,15 +184,25 @@ struct bsw_ctx {
   hipStream_t stream = nullptr;
   // ev[0] start, ev[1] binning done, ev[2] before the DP kernels, ev[3] end
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // one event after each DP launch, and what each launch ran
+  static constexpr int MAXL = NCLS + 2;
+  hipEvent_t lev[MAXL] = {};
+  int lcls[MAXL] = {};
+  int n_launch = 0;
+  double lms[MAXL] = {};
+  unsigned long long lcells[MAXL] = {};
   DevBuf ws;       // workspace
   DevBuf in;       // staged host inputs
   DevBuf res;      // staged results (host API)
   DevBuf longbuf;  // row buffers of the long class
+  DevBuf qtiles;   // column-major query tiles of the 8-bit lane kernels
   KParams* h_kp = nullptr;  // pinned
   KParams* d_kp = nullptr;
   Status* h_status = nullptr;  // pinned
-  int64_t* h_cls = nullptr;    // pinned [NCLS][2]
+  long long* h_cls = nullptr;  // pinned [NCLS][2]
   int blocks_per_cu[2][NCLS] = {};
+  // occupancy of the 8-bit classes by (symmetric variant, ring chunks)
+  int occ8[2][NL8][80] = {};
   int last_status = BSW_OK;
   bool pending = false;
   hipStream_t pending_stream = nullptr;
@@ -207,6 +223,12 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
                  const uint8_t* t, const uint64_t* t_off, const int32_t* h0,
                  const uint8_t* pid, int32_t n_params, bsw_result* out,
                  bsw_diag* diag, hipStream_t s) {
+  int wmax = 0;
+  bool sym = true;
+  for (int i = 0; i < n_params; ++i) {
+    wmax = std::max(wmax, c->h_kp[i].w);
+    sym = sym && c->h_kp[i].o_del == c->h_kp[i].o_ins && c->h_kp[i].e_del == c->h_kp[i].e_ins;
+  }
   const Layout L = layout_for(n);
   int rc = c->ws.ensure(L.total);
   if (rc) return rc;
@@ -215,7 +237,8 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
   Status* st = (Status*)(base + L.status);
   uint32_t* ctr = (uint32_t*)(base + L.ctr);
   uint32_t* cursor = (uint32_t*)(base + L.cursor);
-  int64_t* cls_range = (int64_t*)(base + L.cls_range);
+  long long* cls_range = (long long*)(base + L.cls_range);
+  PairDesc* ovf = (PairDesc*)(base + L.ovf);
   uint32_t* keys = (uint32_t*)(base + L.keys);
   PairDesc* desc = (PairDesc*)(base + L.desc);
 
@@ -232,7 +255,7 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(c->ev[1], s));
   HIPCHK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(c->h_cls, cls_range, sizeof(int64_t) * 2 * NCLS,
+  HIPCHK(hipMemcpyAsync(c->h_cls, cls_range, sizeof(long long) * 2 * NCLS,
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (c->h_status->bad)
@@ -240,21 +263,49 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
                 ~(unsigned long long)c->h_status->first_bad_inv);
 
   const bool persist = c->opts.path != BSW_PATH_PLAIN;
-  c->n_dp_launches = 0;
-  HIPCHK(hipEventRecord(c->ev[2], s));
-  for (int cls = 0; cls < CLS_LANE_END; ++cls) {
+  // grid of every lane class, and the query-tile space of the 8-bit ones
+  int64_t blocks[NCLS] = {};
+  int ring[NCLS] = {};
+  size_t qt_off[NCLS] = {}, qt_words = 0;
+  bool any8 = false;
+  for (int cls = 0; cls < CLS_LONG; ++cls) {
     const int64_t count = c->h_cls[2 * cls + 1];
     if (count <= 0) continue;
     const int wpb = lane_waves_per_block(cls);
     const int64_t tiles = (count + 63) / 64;
-    int64_t blocks = (tiles + wpb - 1) / wpb;
-    if (persist) {
-      const int64_t cap = (int64_t)c->blocks_per_cu[1][cls] * c->num_cu;
-      blocks = std::min(blocks, cap);
+    blocks[cls] = (tiles + wpb - 1) / wpb;
+    int per_cu = c->blocks_per_cu[1][cls];
+    if (cls < CLS_W16) {
+      ring[cls] = lane8_ring_chunks(cls, wmax);
+      int& occ = c->occ8[sym ? 1 : 0][cls - CLS_L8][ring[cls]];
+      if (!occ) occ = lane_blocks_per_cu(cls, sym, (size_t)ring[cls] * 512);
+      per_cu = occ;
     }
-    launch_lane(cls, persist, (unsigned)blocks, desc, cls_range, q, t, c->d_kp, out,
-                diag, ctr + cls, st, s);
+    if (persist) blocks[cls] = std::min(blocks[cls], (int64_t)per_cu * c->num_cu);
+    if (cls < CLS_W16) {
+      any8 = true;
+      qt_off[cls] = qt_words;
+      qt_words += (size_t)blocks[cls] * lane8_qtile_words(cls);
+    }
+  }
+  if (qt_words && (rc = c->qtiles.ensure(qt_words * 4))) return rc;
+  uint32_t* qt = (uint32_t*)c->qtiles.p;
+  c->n_dp_launches = 0;
+  c->n_launch = 0;
+  HIPCHK(hipEventRecord(c->ev[2], s));
+  auto mark = [&](int cls) -> int {
+    c->lcls[c->n_launch] = cls;
+    HIPCHK(hipEventRecord(c->lev[c->n_launch], s));
+    ++c->n_launch;
     ++c->n_dp_launches;
+    return BSW_OK;
+  };
+  for (int cls = 0; cls < CLS_LONG; ++cls) {
+    if (blocks[cls] <= 0) continue;
+    launch_lane(cls, persist, (unsigned)blocks[cls], desc, cls_range + 2 * cls, q, t,
+                c->d_kp, out, diag, ctr + cls, st, qt ? qt + qt_off[cls] : nullptr, ovf,
+                st, ring[cls], sym, &st->cls_cells[cls], s);
+    if ((rc = mark(cls))) return rc;
   }
   if (c->h_cls[2 * CLS_LONG + 1] > 0) {
     const size_t need = (size_t)LONG_SLOTS * LONG_SLOT_COLS * (sizeof(int2) + 1);
@@ -262,9 +313,20 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
     if (rc) return rc;
     int2* gbuf = (int2*)c->longbuf.p;
     uint8_t* gq = (uint8_t*)(gbuf + (size_t)LONG_SLOTS * LONG_SLOT_COLS);
-    launch_long(desc, cls_range, q, t, c->d_kp, out, diag, ctr + CLS_LONG, gbuf, gq, st, s);
-    ++c->n_dp_launches;
+    launch_long(desc, cls_range + 2 * CLS_LONG, q, t, c->d_kp, out, diag, ctr + CLS_LONG,
+                gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
+    if ((rc = mark(CLS_LONG))) return rc;
   }
+  if (any8) {
+    // 16-bit rerun of the pairs the 8-bit kernels could not settle; the
+    // count is only known on the device, so the grid is persistent
+    const int rcls = CLS_W16 + NLW - 1;
+    launch_lane(rcls, true, (unsigned)(c->blocks_per_cu[1][rcls] * c->num_cu), ovf,
+                st->ovf_range, q, t, c->d_kp, out, diag, ctr + NCLS, st, nullptr, nullptr,
+                st, 0, false, &st->cls_cells[NCLS], s);
+    if ((rc = mark(NCLS))) return rc;
+  }
+  HIPCHK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(c->ev[3], s));
   return BSW_OK;
@@ -280,6 +342,14 @@ void record_timing(bsw_ctx* c) {
     c->timing[1] = a;
     c->timing[2] = b;
     c->timing[3] = c->n_dp_launches;
+  }
+  hipEvent_t prev = c->ev[2];
+  for (int k = 0; k < c->n_launch; ++k) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, prev, c->lev[k]) != hipSuccess) ms = 0;
+    c->lms[k] = ms;
+    c->lcells[k] = c->h_status->cls_cells[c->lcls[k]];
+    prev = c->lev[k];
   }
 }
 
@@ -325,6 +395,8 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
   }
   for (auto& e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) rc = BSW_EDEVICE;
+  for (auto& e : c->lev)
+    if (hipEventCreate(&e) != hipSuccess) rc = BSW_EDEVICE;
   if (hipHostMalloc((void**)&c->h_kp, sizeof(KParams) * 256, 0) != hipSuccess ||
       hipHostMalloc((void**)&c->h_status, sizeof(Status), 0) != hipSuccess ||
       hipHostMalloc((void**)&c->h_cls, sizeof(int64_t) * 2 * NCLS, 0) != hipSuccess ||
@@ -332,10 +404,10 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
     rc = BSW_ENOMEM;
   // raise the dynamic-LDS limit of the large lane classes; a refusal only
   // surfaces later as a launch error of that class
-  for (int cls = 0; cls < CLS_LANE_END && rc == BSW_OK; ++cls)
+  for (int cls = 0; cls < CLS_LONG && rc == BSW_OK; ++cls)
     for (int p = 0; p < 2; ++p) {
       (void)lane_setup(cls, p == 1);
-      c->blocks_per_cu[p][cls] = lane_blocks_per_cu(cls, p == 1);
+      c->blocks_per_cu[p][cls] = lane_blocks_per_cu(cls, p == 1, 0);
     }
   (void)hipGetLastError();
   if (rc != BSW_OK) {
@@ -354,11 +426,14 @@ void bsw_ctx_destroy(bsw_ctx* c) {
   c->in.release();
   c->res.release();
   c->longbuf.release();
+  c->qtiles.release();
   if (c->h_kp) (void)hipHostFree(c->h_kp);
   if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->h_cls) (void)hipHostFree(c->h_cls);
   if (c->d_kp) (void)hipFree(c->d_kp);
   for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->lev)
     if (e) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -399,6 +474,27 @@ int bsw_ctx_wait(bsw_ctx* c) {
   HIPCHK(hipStreamSynchronize(c->pending_stream));
   record_timing(c);
   return BSW_OK;
+}
+
+int bsw_ctx_last_kernels(bsw_ctx* c, int32_t* cls, int64_t* cells, double* ms,
+                         int32_t max) {
+  if (!c) return fail(BSW_EINVAL, "ctx is NULL");
+  const int n = std::min((int)max, c->n_launch);
+  for (int k = 0; k < n; ++k) {
+    if (cls) cls[k] = c->lcls[k];
+    if (cells) cells[k] = (int64_t)c->lcells[k];
+    if (ms) ms[k] = c->lms[k];
+  }
+  return c->n_launch;
+}
+
+const char* bsw_class_name(int32_t cls) {
+  static const char* names[NCLS + 1] = {
+      "lane8_q32",  "lane8_q64",  "lane8_q96",  "lane8_q128", "lane8_q160",
+      "lane8_q192", "lane8_q224", "lane8_q256", "lane16_q32", "lane16_q64",
+      "lane16_q128", "lane16_q256", "lane32_q32", "lane32_q64", "lane32_q128",
+      "lane32_q256", "long", "rerun16"};
+  return cls >= 0 && cls <= NCLS ? names[cls] : "?";
 }
 
 int bsw_ctx_last_timing(bsw_ctx* c, double out4[4]) {

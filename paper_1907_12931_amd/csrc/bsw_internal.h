@@ -27,16 +27,27 @@ struct KParams {
   int32_t pad_[2];
 };
 
-// Kernel classes.  Lane mode: one pair per lane, the row buffer of H and E
-// in LDS, sized by the class's query-length cap.  Value width: stored H and
-// E of a pair never exceed U = h0 + A * min(qlen, tlen), so 8-bit records
-// are exact when U <= 255 and 16-bit records when U <= 65535.
-enum { W8 = 0, W16 = 1, W32 = 2, NWIDTH = 3 };
-enum { NLQ = 4 };                        // query caps 32, 64, 128, 256
-constexpr int LQ_CAP[NLQ] = {32, 64, 128, 256};
-enum { CLS_LANE_END = NLQ * NWIDTH,      // 12 lane classes
-       CLS_LONG = CLS_LANE_END,          // query longer than 256
-       NCLS = CLS_LANE_END + 1 };
+// Kernel classes (all lane mode: one pair per lane of a wave).
+//  * L8 classes: 8-bit row-buffer records (H and E bytes), used for every
+//    pair whose query fits the class cap, unless a wider width is forced.
+//    A pair whose bound U = h0 + A*min(qlen,tlen) exceeds 255 runs here
+//    speculatively: its final best score tells whether any stored value can
+//    have exceeded 8 bits (best + max(0, A - o_del - e_del) > 255), and
+//    such pairs are run again with 16-bit records.
+//  * W16 / W32 classes: 16- or 32-bit records for pairs whose bound (or a
+//    forced minimum width) needs them, and for the 8-bit overflow reruns.
+//  * LONG: queries longer than 256.
+enum { W8 = 0, W16 = 1, W32 = 2 };
+enum { NL8 = 8, NLW = 4 };
+constexpr int L8_CAP[NL8] = {32, 64, 96, 128, 160, 192, 224, 256};
+constexpr int LW_CAP[NLW] = {32, 64, 128, 256};
+enum {
+  CLS_L8 = 0,                      // 8 classes
+  CLS_W16 = CLS_L8 + NL8,          // 4 classes
+  CLS_W32 = CLS_W16 + NLW,         // 4 classes
+  CLS_LONG = CLS_W32 + NLW,        // queries longer than 256
+  NCLS = CLS_LONG + 1
+};
 
 constexpr int KEY_SUB_BITS = 12;         // sub-key inside a class
 constexpr int NBINS = NCLS << KEY_SUB_BITS;
@@ -47,6 +58,8 @@ struct Status {
   uint32_t pad_;
   unsigned long long first_bad_inv;  // ~(smallest bad pair index); 0 = none
   unsigned long long long_max;   // largest query length in the long class
+  long long ovf_range[2];        // {0, number of 8-bit overflow reruns}
+  unsigned long long cls_cells[32];  // band cells per class (+ rerun slot)
 };
 
 constexpr int LONG_SLOTS = 256;          // waves running the long class

@@ -80,6 +80,13 @@ __device__ __forceinline__ uint32_t wave_first(uint32_t v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// 64-bit wave sum (per-class cell counters).
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // preparation kernels
 
@@ -112,22 +119,31 @@ __global__ void k_prep(int64_t n, const uint64_t* __restrict__ q_off,
       continue;
     }
     const int ql = (int)(qe - qo), tl = (int)(te - to);
+    const KParams& P = kp[p];
     // bound on every stored H and E of the pair (Sec. 5.4.1 precision)
-    const int64_t U = (int64_t)hh + (int64_t)kp[p].amax * (ql < tl ? ql : tl);
+    const int64_t U = (int64_t)hh + (int64_t)P.amax * (ql < tl ? ql : tl);
     int wd = U <= 255 ? W8 : (U <= 65535 ? W16 : W32);
     if (min_bits >= 16 && wd < W16) wd = W16;
     if (min_bits >= 32) wd = W32;
     (void)force_mode;
+    // 16-bit pairs start at 8 bits when the seed itself leaves room
+    const int slack = P.amax - P.oe_del > 0 ? P.amax - P.oe_del : 0;
+    const bool spec8 = wd == W8 || (wd == W16 && min_bits < 16 && hh + slack <= 255);
     int cls, cap;
-    if (ql > LQ_CAP[NLQ - 1]) {
+    if (ql > 256) {
       cls = CLS_LONG;
       cap = BSW_MAX_LEN;
       atomicMax(&st->long_max, (unsigned long long)ql);
+    } else if (spec8) {
+      int c = 0;
+      while (L8_CAP[c] < ql) ++c;
+      cls = CLS_L8 + c;
+      cap = L8_CAP[c];
     } else {
       int c = 0;
-      while (LQ_CAP[c] < ql) ++c;
-      cls = c * NWIDTH + wd;
-      cap = LQ_CAP[c];
+      while (LW_CAP[c] < ql) ++c;
+      cls = (wd == W16 ? CLS_W16 : CLS_W32) + c;
+      cap = LW_CAP[c];
     }
     // longest first inside a class: larger query, then larger target
     int qq = (int)((int64_t)ql * 64 / (cap + 1));
@@ -190,7 +206,7 @@ __global__ void k_codes(const uint8_t* __restrict__ s,
 // One block: exclusive scan of hist into cursor, class ranges.
 __global__ void __launch_bounds__(1024)
 k_scan(const uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor,
-       int64_t* __restrict__ cls_range) {
+       long long* __restrict__ cls_range) {
   __shared__ uint32_t part[1024];
   constexpr int PER = (NBINS + 1023) / 1024;
   const int tid = threadIdx.x;
@@ -218,8 +234,8 @@ k_scan(const uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor,
   __syncthreads();
   if (tid < NCLS) {
     // count of class tid = start of the next class - own start
-    const int64_t beg = cls_range[2 * tid];
-    const int64_t end = tid + 1 < NCLS ? cls_range[2 * (tid + 1)] : (int64_t)part[1023];
+    const long long beg = cls_range[2 * tid];
+    const long long end = tid + 1 < NCLS ? cls_range[2 * (tid + 1)] : (long long)part[1023];
     cls_range[2 * tid + 1] = end - beg;
   }
 }
@@ -256,7 +272,7 @@ __global__ void k_scatter(int64_t n, const uint64_t* __restrict__ q_off,
 // lanes of a wave hit distinct banks; S = 1 for a private buffer)
 
 template <int W, int S>
-__device__ __forceinline__ void extend_pair(const PairDesc& pd, const KParams& P,
+__device__ __forceinline__ long long extend_pair(const PairDesc& pd, const KParams& P,
                                             const uint8_t* __restrict__ q,
                                             const uint8_t* __restrict__ t,
                                             typename Rec<W>::T* hb, uint8_t* qb,
@@ -362,17 +378,20 @@ __device__ __forceinline__ void extend_pair(const PairDesc& pd, const KParams& P
     dg.cells = cells;
     diag[pd.idx] = dg;
   }
+  return cells;
 }
 
-// Lane mode: one wave runs a tile of 64 pairs of one class.  PERSIST: waves
-// pull tiles from a counter until the class is done (tiles are in
-// longest-first order); otherwise wave w of the grid runs tile w.
+// Lane mode with wide records: one wave runs a tile of 64 pairs of one
+// class; range = {first pair, pair count} in desc.  PERSIST: waves pull
+// tiles from a counter until the class is done (tiles are in longest-first
+// order); otherwise wave w of the grid runs tile w.
 template <int W, int LQCAP, bool PERSIST>
 __global__ void __launch_bounds__(256)
-k_lane(const PairDesc* __restrict__ desc, const int64_t* __restrict__ cls_range,
-       int cls, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
+k_lane(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
+       const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
        const KParams* __restrict__ kp, bsw_result* __restrict__ out,
-       bsw_diag* __restrict__ diag, uint32_t* tile_ctr, const Status* st) {
+       bsw_diag* __restrict__ diag, uint32_t* tile_ctr, const Status* st,
+       unsigned long long* __restrict__ cls_cells) {
   if (st->bad) return;
   using T = typename Rec<W>::T;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -381,9 +400,10 @@ k_lane(const PairDesc* __restrict__ desc, const int64_t* __restrict__ cls_range,
   constexpr size_t PER_WAVE = HB_BYTES + (size_t)LQCAP * 64;
   T* hb = (T*)(smem + wv * PER_WAVE) + lane;
   uint8_t* qb = smem + wv * PER_WAVE + HB_BYTES + lane;
-  const int64_t begin = cls_range[2 * cls], count = cls_range[2 * cls + 1];
+  const long long begin = range[0], count = range[1];
   const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
   uint32_t tile = blockIdx.x * (blockDim.x >> 6) + wv;
+  unsigned long long acc = 0;
   for (;;) {
     if (PERSIST) {
       uint32_t v = 0;
@@ -391,25 +411,340 @@ k_lane(const PairDesc* __restrict__ desc, const int64_t* __restrict__ cls_range,
       tile = wave_first(__shfl(v, 0));
     }
     if (tile >= ntiles) break;
-    const int64_t k = (int64_t)tile * 64 + lane;
+    const long long k = (long long)tile * 64 + lane;
     if (k < count) {
       const PairDesc pd = desc[begin + k];
-      extend_pair<W, 64>(pd, kp[pd.pid], q, t, hb, qb, out, diag);
+      acc += (unsigned long long)extend_pair<W, 64>(pd, kp[pd.pid], q, t, hb, qb, out,
+                                                    diag);
     }
     if (!PERSIST) break;
   }
+  acc = wave_sum64(acc);
+  if (lane == 0 && acc) atomicAdd(cls_cells, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Lane mode with 8-bit records (the main kernel).
+//
+// Every lane of the wave owns one pair; the wave walks rows in lock step
+// and, inside a row, walks the same column j in every lane (each lane masks
+// columns at or past its band end; columns left of its band start compute
+// zeros because the buffer there is kept at zero), so the row buffer can be
+// laid out column-major: chunk c of four columns for lane l is one 8-byte
+// LDS word at [c][l], bytes (H0,E0,H1,E1,H2,E2,H3,E3), and the four query
+// codes of a chunk are one dword at [c][l] of a per-wave tile in HBM.  One
+// LDS read, one LDS write, one global read and one v_perm (four scores)
+// serve four cells.  Column CAP is the right-edge slot.
+//
+// Values are stored as bytes.  A pair that may exceed 8 bits is detected
+// from its final best score (all stored H are <= best; stored E are
+// <= best + max(0, A - o_del - e_del)); it is then not written but queued
+// for a 16-bit rerun.
+
+// Wave-wide min / max of a per-lane value, returned as a wave-uniform
+// scalar: four DPP steps reduce each row of 16 lanes (swap neighbours, swap
+// pairs, half-row mirror, row mirror), then the four row results are read
+// out and combined on the scalar unit.  Every lane must be active.
+__device__ __forceinline__ int wave_min(int v) {
+  v = imin(v, __builtin_amdgcn_update_dpp(v, v, 0xb1, 0xf, 0xf, false));
+  v = imin(v, __builtin_amdgcn_update_dpp(v, v, 0x4e, 0xf, 0xf, false));
+  v = imin(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));
+  v = imin(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));
+  const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return imin(imin(a, b), imin(c, d));
+}
+__device__ __forceinline__ int wave_max(int v) {
+  v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0xb1, 0xf, 0xf, false));
+  v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x4e, 0xf, 0xf, false));
+  v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));
+  v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));
+  const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return imax(imax(a, b), imax(c, d));
+}
+
+// One band cell of the 8-bit kernel on the byte pair (H, E) at bit offset
+// sh of word w, query score byte sb of sc; updates hl, f, mkey and writes
+// the new pair (H(i, j-1), E(i+1, j)) into nw.  Values above 255 only occur
+// in pairs that are rerun, so the packing does not mask them.
+#define BSW_CELL8(w, sh, sc, sb, j, nw, nsh)                                  \
+  {                                                                           \
+    const int d_ = ((w) >> (sh)) & 0xff;                                      \
+    const int e_ = ((w) >> ((sh) + 8)) & 0xff;                                \
+    const int s_ = (int)(int8_t)((sc) >> (8 * (sb)));                         \
+    const int M_ = d_ ? d_ + s_ : 0;                                          \
+    const int h_ = imax(imax(M_, e_), f);                                     \
+    const int en_ = imax(imax(e_ - eD, M_ - oeD), 0);                         \
+    nw |= ((uint32_t)hl | ((uint32_t)en_ << 8)) << (nsh);                     \
+    hl = h_;                                                                  \
+    mkey = imax(mkey, (int)(((uint32_t)h_ << 9) | (uint32_t)(j)));            \
+    f = imax(imax(f - eI, M_ - oeI), 0);                                      \
+  }
+
+// Row buffer in a ring of RC chunks: the band of row i lies in
+// [i - w', i + w' + 1] and nothing outside [beg, highest index written]
+// is ever read again, so with 4*RC > 2w' + 4 no live column shares a
+// slot with another live column.  Columns are initialised lazily (first-
+// row value of Eq. (3)) the first time the band end reaches them.  With
+// RC = CAP/4 + 1 the ring never wraps.
+__device__ __forceinline__ int ring_slot(int chunk, int rc) {
+  return chunk >= rc ? chunk - rc : chunk;
+}
+
+template <int CAP, bool SYM>
+__global__ void __launch_bounds__(64)
+k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
+        const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
+        const KParams* __restrict__ kp, bsw_result* __restrict__ out,
+        bsw_diag* __restrict__ diag, uint32_t* tile_ctr, const Status* st,
+        uint32_t* __restrict__ qtiles, PairDesc* __restrict__ ovf,
+        Status* __restrict__ stw, int persist, int RC,
+        unsigned long long* __restrict__ cls_cells) {
+  if (st->bad) return;
+  extern __shared__ __align__(16) uint2 rb[];  // [RC][64]
+  const int lane = threadIdx.x;
+  uint32_t* qt = qtiles + (size_t)blockIdx.x * (CAP / 4 + 2) * 64 + lane;
+  uint2* my = rb + lane;
+  unsigned char* myb = (unsigned char*)(rb + lane);  // byte view, stride 512
+  // byte address of column x's (H, E) pair in this lane's ring
+#define COL(x) (myb + ring_slot((x) >> 2, RC) * 512 + ((x) & 3) * 2)
+  const long long begin = range[0], count = range[1];
+  const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
+  uint32_t tile = blockIdx.x;
+  unsigned long long tile_cells_acc = 0;
+  for (;;) {
+    if (persist) {
+      uint32_t v = 0;
+      if (lane == 0) v = atomicAdd(tile_ctr, 1u);
+      tile = wave_first(__shfl(v, 0));
+    }
+    if (tile >= ntiles) break;
+    const long long k = (long long)tile * 64 + lane;
+    const bool valid = k < count;
+    PairDesc pd;
+    if (valid) {
+      pd = desc[begin + k];
+    } else {
+      pd.qo = pd.to = 0;
+      pd.ql = pd.tl = 0;
+      pd.h0 = 1;
+      pd.idx = 0;
+      pd.pid = 0;
+    }
+    const KParams& P = kp[pd.pid];
+    const int Lq = pd.ql, Lt = valid ? pd.tl : 0, h0 = pd.h0;
+    const int oD = P.o_del, eD = P.e_del, oI = P.o_ins, eI = P.e_ins;
+    const int oeD = P.oe_del, oeI = SYM ? P.oe_del : P.oe_ins, zd = P.zdrop;
+    const int wb = band_cap(P, Lq);
+    uint32_t pl[5], ph[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      pl[a] = P.prow[a][0];
+      ph[a] = P.prow[a][1];
+    }
+    // first row of Eq. (3): H(-1, j-1) = max(0, h0 - o_ins - e_ins*j), E = 0,
+    // for the columns the ring holds at the start; the rest come lazily
+    int hw = imin(Lq, 4 * RC - 1);  // highest initialised column
+    for (int c = 0; c < RC; ++c) {
+      uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int j = 4 * c + cc;
+        const int h = j == 0 ? h0 : imax(0, h0 - oI - eI * j);
+        const uint32_t hv = j <= hw ? (uint32_t)imin(h, 255) : 0u;
+        if (cc < 2) w0 |= hv << (16 * cc); else w1 |= hv << (16 * (cc - 2));
+      }
+      my[c * 64] = make_uint2(w0, w1);
+    }
+    // query codes, four per dword, column-major tile
+    {
+      const uint8_t* qs = q + pd.qo;
+      const int nq = (Lq + 3) >> 2;
+      for (int c = 0; c < CAP / 4; ++c) {
+        uint32_t w = 0;
+        if (c < nq) {
+          const int j = 4 * c;
+          w = (uint32_t)qs[j];
+          if (j + 1 < Lq) w |= (uint32_t)qs[j + 1] << 8;
+          if (j + 2 < Lq) w |= (uint32_t)qs[j + 2] << 16;
+          if (j + 3 < Lq) w |= (uint32_t)qs[j + 3] << 24;
+        }
+        qt[c * 64] = w;
+      }
+    }
+
+    int best = h0, bi = -1, bj = -1, gbest = -1, gi = -1, moff = 0;
+    int beg = 0, end = Lq, rows = 0, stop = 0;
+    long long cells = 0;
+    bool live = valid && Lt > 0;
+    const uint8_t* ts = t + pd.to;
+    int tb_next = live ? ts[0] : 0;
+    for (int i = 0;; ++i) {
+      live = live && i < Lt;
+      if (__ballot(live) == 0) break;
+      int hl = 0, f = 0;
+      uint32_t lo = 0, hi = 0;
+      if (live) {
+        ++rows;
+        // band (Sec. 5.1 (a)); the column leaving on the left is zeroed so
+        // that everything left of beg stays zero
+        if (beg < i - wb) {
+          *(unsigned short*)COL(beg) = 0;
+          beg = i - wb;
+        }
+        end = imin(imin(end, i + wb + 1), Lq);
+        if (end > beg) cells += end - beg;
+        // columns entering the ring for the first time get their first-row
+        // value
+        while (hw < end) {
+          ++hw;
+          *(unsigned short*)COL(hw) = (unsigned short)imax(0, h0 - oI - eI * hw);
+        }
+        const int tb = tb_next;
+        tb_next = i + 1 < Lt ? ts[i + 1] : 0;
+        lo = pl[0];
+        hi = ph[0];
+#pragma unroll
+        for (int a = 1; a < 5; ++a) {
+          lo = tb == a ? pl[a] : lo;
+          hi = tb == a ? ph[a] : hi;
+        }
+        hl = beg == 0 ? imax(0, h0 - oD - eD * (i + 1)) : 0;
+      }
+      const int rend = live ? end : 0;  // columns >= rend are masked
+      // chunks [c0, cf) are inside the band end of every live lane and run
+      // unmasked (dead lanes compute on their own private buffer, unused);
+      // chunks [cf, c1) mask columns at or past each lane's end
+      const int c0 = wave_min(live ? (beg >> 2) : 0x7fffffff);
+      const int cf = wave_min(live ? (rend >> 2) : 0x7fffffff);
+      const int c1 = wave_max(live ? ((rend + 3) >> 2) : 0);
+      int mkey = 0;
+      int c = c0;
+      if (c < cf) {
+        int sl = ring_slot(c, RC);
+        uint2 ch = my[sl * 64];
+        uint32_t q0 = qt[c * 64], q1 = qt[(c + 1) * 64];
+        for (; c < cf; ++c) {
+          int sn = sl + 1;
+          sn = sn == RC ? 0 : sn;
+          // next chunk's buffer word and the query two chunks ahead
+          const uint2 chn = my[sn * 64];
+          const uint32_t q2 = qt[(c + 2) * 64];
+          const uint32_t sc = __builtin_amdgcn_perm(hi, lo, q0);
+          const int j0 = 4 * c;
+          uint32_t n0 = 0, n1 = 0;
+          BSW_CELL8(ch.x, 0, sc, 0, j0, n0, 0);
+          BSW_CELL8(ch.x, 16, sc, 1, j0 + 1, n0, 16);
+          BSW_CELL8(ch.y, 0, sc, 2, j0 + 2, n1, 0);
+          BSW_CELL8(ch.y, 16, sc, 3, j0 + 3, n1, 16);
+          my[sl * 64] = make_uint2(n0, n1);
+          sl = sn;
+          ch = chn;
+          q0 = q1;
+          q1 = q2;
+        }
+      }
+      for (; c < c1; ++c) {
+        const int j0 = 4 * c;
+        if (j0 < rend) {
+          const int sl = ring_slot(c, RC);
+          uint2 ch = my[sl * 64];
+          const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qt[c * 64]);
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            const int j = j0 + cc;
+            if (j < rend) {
+              uint32_t& w = cc < 2 ? ch.x : ch.y;
+              const int sh = 16 * (cc & 1);
+              uint32_t nw = 0;
+              BSW_CELL8(w, sh, sc, cc, j, nw, 0);
+              w = (w & ~(0xffffu << sh)) | ((nw & 0xffffu) << sh);
+            }
+          }
+          my[sl * 64] = ch;
+        }
+      }
+      if (live) {
+        // right edge (R8): H(i, end-1) at index end; E there is already 0
+        *(unsigned short*)COL(end) = (unsigned short)(hl & 0xff);
+        // best score touching the end of the query (Sec. 5.4 (b))
+        if (imax(beg, end) == Lq) {
+          gi = hl >= gbest ? i : gi;
+          gbest = imax(gbest, hl);
+        }
+        const int m = mkey >> 9, mj = mkey & 511;
+        if (m == 0) {
+          stop = 1;
+          live = false;
+        } else if (m > best) {
+          best = m;
+          bi = i;
+          bj = mj;
+          moff = imax(moff, mj > i ? mj - i : i - mj);
+        } else if (zd > 0) {
+          const int drift = (i - bi) - (mj - bj);
+          const int drop = best - m - (drift > 0 ? drift * eD : -drift * eI);
+          if (drop > zd) {
+            stop = 2;
+            live = false;
+          }
+        }
+        if (live) {
+          // shrink the band by its empty ends (Sec. 5.1 (c))
+          while (beg < end && *(const unsigned short*)COL(beg) == 0) ++beg;
+          int x = end;
+          while (x >= beg && *(const unsigned short*)COL(x) == 0) --x;
+          end = imin(x + 2, Lq);
+        }
+      }
+    }
+    unsigned long long my_cells = 0;
+    if (valid) {
+      const int slack = P.amax - oeD > 0 ? P.amax - oeD : 0;
+      if (best + slack > 255) {
+        // some stored value may have needed more than 8 bits: rerun wide
+        const unsigned long long pos =
+            atomicAdd((unsigned long long*)&stw->ovf_range[1], 1ull);
+        ovf[pos] = pd;
+      } else {
+        my_cells = (unsigned long long)cells;
+        bsw_result res;
+        res.score = best;
+        res.qle = bj + 1;
+        res.tle = bi + 1;
+        res.gtle = gi + 1;
+        res.gscore = gbest;
+        res.max_off = moff;
+        out[pd.idx] = res;
+        if (diag) {
+          bsw_diag dg;
+          dg.rows = rows;
+          dg.stop = stop;
+          dg.cells = cells;
+          diag[pd.idx] = dg;
+        }
+      }
+    }
+    tile_cells_acc += my_cells;
+    if (!persist) break;
+  }
+  tile_cells_acc = wave_sum64(tile_cells_acc);
+  if (lane == 0 && tile_cells_acc) atomicAdd(cls_cells, tile_cells_acc);
+#undef COL
 }
 
 // Queries longer than 256: one pair per wave, lane 0 runs it with a
 // 32-bit row buffer in HBM (slot per wave); waves pull pairs from a counter.
 __global__ void __launch_bounds__(64)
-k_long(const PairDesc* __restrict__ desc, const int64_t* __restrict__ cls_range,
+k_long(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
        const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
        const KParams* __restrict__ kp, bsw_result* __restrict__ out,
        bsw_diag* __restrict__ diag, uint32_t* ctr, int2* __restrict__ gbuf,
-       uint8_t* __restrict__ gq, const Status* st) {
+       uint8_t* __restrict__ gq, const Status* st,
+       unsigned long long* __restrict__ cls_cells) {
   if (st->bad) return;
-  const int64_t begin = cls_range[2 * CLS_LONG], count = cls_range[2 * CLS_LONG + 1];
+  const long long begin = range[0], count = range[1];
   int2* hb = gbuf + (size_t)blockIdx.x * LONG_SLOT_COLS;
   uint8_t* qb = gq + (size_t)blockIdx.x * LONG_SLOT_COLS;
   for (;;) {
@@ -419,7 +754,8 @@ k_long(const PairDesc* __restrict__ desc, const int64_t* __restrict__ cls_range,
     if (k >= count) break;
     if (threadIdx.x == 0) {
       const PairDesc pd = desc[begin + k];
-      extend_pair<W32, 1>(pd, kp[pd.pid], q, t, hb, qb, out, diag);
+      const long long c = extend_pair<W32, 1>(pd, kp[pd.pid], q, t, hb, qb, out, diag);
+      atomicAdd(cls_cells, (unsigned long long)c);
     }
   }
 }
@@ -431,62 +767,91 @@ k_long(const PairDesc* __restrict__ desc, const int64_t* __restrict__ cls_range,
 
 namespace bsw {
 
-template <int W, int LQ>
-constexpr size_t lane_wave_bytes() {
-  return (size_t)(LQ + 1) * 64 * sizeof(typename Rec<W>::T) + (size_t)LQ * 64;
+static int cls_cap(int cls) {
+  if (cls < CLS_W16) return L8_CAP[cls - CLS_L8];
+  if (cls < CLS_W32) return LW_CAP[cls - CLS_W16];
+  return LW_CAP[cls - CLS_W32];
 }
 
+// LDS bytes per wave of a class
 size_t lane_lds_per_wave(int cls) {
-  const int w = cls % NWIDTH, c = cls / NWIDTH;
-  const size_t rec = w == W8 ? 2 : (w == W16 ? 4 : 8);
-  return (size_t)(LQ_CAP[c] + 1) * 64 * rec + (size_t)LQ_CAP[c] * 64;
+  const int cap = cls_cap(cls);
+  if (cls < CLS_W16) return (size_t)(cap / 4 + 1) * 64 * 8;
+  const size_t rec = cls < CLS_W32 ? 4 : 8;
+  return (size_t)(cap + 1) * 64 * rec + (size_t)cap * 64;
 }
 
-// waves per workgroup: as many as fit in 64 KiB of LDS (1..4)
+// waves per workgroup: 8-bit classes run one wave per group; wide classes
+// as many as fit in 64 KiB of LDS (1..4)
 int lane_waves_per_block(int cls) {
+  if (cls < CLS_W16) return 1;
   const size_t b = lane_lds_per_wave(cls);
   int w = (int)(65536 / b);
   return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
-typedef void (*LaneFn)(const PairDesc*, const int64_t*, int, const uint8_t*,
+typedef void (*LaneFn)(const PairDesc*, const long long*, const uint8_t*,
                        const uint8_t*, const KParams*, bsw_result*, bsw_diag*,
-                       uint32_t*, const Status*);
+                       uint32_t*, const Status*, unsigned long long*);
+typedef void (*Lane8Fn)(const PairDesc*, const long long*, const uint8_t*,
+                        const uint8_t*, const KParams*, bsw_result*, bsw_diag*,
+                        uint32_t*, const Status*, uint32_t*, PairDesc*, Status*, int,
+                        int, unsigned long long*);
 
-template <int W, int C, bool P>
-static LaneFn lane_fn_one() {
-  return k_lane<W, LQ_CAP[C], P>;
+static Lane8Fn lane8_fn(int cls, bool sym) {
+  static const Lane8Fn tab[2][NL8] = {
+      {k_lane8<32, false>, k_lane8<64, false>, k_lane8<96, false>, k_lane8<128, false>,
+       k_lane8<160, false>, k_lane8<192, false>, k_lane8<224, false>, k_lane8<256, false>},
+      {k_lane8<32, true>, k_lane8<64, true>, k_lane8<96, true>, k_lane8<128, true>,
+       k_lane8<160, true>, k_lane8<192, true>, k_lane8<224, true>, k_lane8<256, true>}};
+  return tab[sym ? 1 : 0][cls - CLS_L8];
 }
 
-static LaneFn lane_fn(int cls, bool persist) {
-  static LaneFn tab[2][CLS_LANE_END] = {
-      {lane_fn_one<W8, 0, false>(), lane_fn_one<W16, 0, false>(), lane_fn_one<W32, 0, false>(),
-       lane_fn_one<W8, 1, false>(), lane_fn_one<W16, 1, false>(), lane_fn_one<W32, 1, false>(),
-       lane_fn_one<W8, 2, false>(), lane_fn_one<W16, 2, false>(), lane_fn_one<W32, 2, false>(),
-       lane_fn_one<W8, 3, false>(), lane_fn_one<W16, 3, false>(), lane_fn_one<W32, 3, false>()},
-      {lane_fn_one<W8, 0, true>(), lane_fn_one<W16, 0, true>(), lane_fn_one<W32, 0, true>(),
-       lane_fn_one<W8, 1, true>(), lane_fn_one<W16, 1, true>(), lane_fn_one<W32, 1, true>(),
-       lane_fn_one<W8, 2, true>(), lane_fn_one<W16, 2, true>(), lane_fn_one<W32, 2, true>(),
-       lane_fn_one<W8, 3, true>(), lane_fn_one<W16, 3, true>(), lane_fn_one<W32, 3, true>()}};
-  return tab[persist ? 1 : 0][cls];
+static LaneFn lanew_fn(int cls, bool persist) {
+  static const LaneFn tab[2][2 * NLW] = {
+      {k_lane<W16, 32, false>, k_lane<W16, 64, false>, k_lane<W16, 128, false>,
+       k_lane<W16, 256, false>, k_lane<W32, 32, false>, k_lane<W32, 64, false>,
+       k_lane<W32, 128, false>, k_lane<W32, 256, false>},
+      {k_lane<W16, 32, true>, k_lane<W16, 64, true>, k_lane<W16, 128, true>,
+       k_lane<W16, 256, true>, k_lane<W32, 32, true>, k_lane<W32, 64, true>,
+       k_lane<W32, 128, true>, k_lane<W32, 256, true>}};
+  return tab[persist ? 1 : 0][cls - CLS_W16];
+}
+
+// kernel symbol of a class (for 8-bit classes "persist" selects the
+// symmetric-gap variant; both take the same LDS)
+static const void* lane_sym(int cls, bool persist) {
+  return cls < CLS_W16 ? (const void*)lane8_fn(cls, persist)
+                       : (const void*)lanew_fn(cls, persist);
 }
 
 hipError_t lane_setup(int cls, bool persist) {
   const size_t lds = lane_lds_per_wave(cls) * lane_waves_per_block(cls);
-  return hipFuncSetAttribute((const void*)lane_fn(cls, persist),
+  return hipFuncSetAttribute(lane_sym(cls, persist),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-// resident workgroups per CU for a lane-mode class
-int lane_blocks_per_cu(int cls, bool persist) {
+// resident workgroups per CU for a lane-mode class, given the LDS bytes
+// per workgroup (0 = the class's full row buffer)
+int lane_blocks_per_cu(int cls, bool persist, size_t lds) {
   int nb = 0;
   const int wpb = lane_waves_per_block(cls);
-  const size_t lds = lane_lds_per_wave(cls) * wpb;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)lane_fn(cls, persist),
-                                                   wpb * 64, lds) != hipSuccess)
+  if (!lds) lds = lane_lds_per_wave(cls) * wpb;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_sym(cls, persist), wpb * 64,
+                                                   lds) != hipSuccess)
     return 1;
   return nb < 1 ? 1 : nb;
 }
+
+// ring chunks of an 8-bit class for band half-widths up to wmax
+int lane8_ring_chunks(int cls, int wmax) {
+  const int full = cls_cap(cls) / 4 + 1;
+  const long long need = (2LL * wmax + 5 + 3) / 4 + 1;
+  return need >= full ? full : (int)need;
+}
+
+// HBM words of query tile per workgroup of an 8-bit class
+size_t lane8_qtile_words(int cls) { return ((size_t)cls_cap(cls) / 4 + 2) * 64; }
 
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s) {
   int64_t blocks = (nwords + 255) / 256;
@@ -510,7 +875,7 @@ void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st
   hipLaunchKernelGGL(k_codes, dim3(4096), dim3(256), 0, s, seq, off, n, st);
 }
 
-void launch_scan(const uint32_t* hist, uint32_t* cursor, int64_t* cls_range,
+void launch_scan(const uint32_t* hist, uint32_t* cursor, long long* cls_range,
                  hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, cursor, cls_range);
 }
@@ -526,21 +891,28 @@ void launch_scatter(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
 }
 
 void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
-                 const int64_t* cls_range, const uint8_t* q, const uint8_t* t,
+                 const long long* range, const uint8_t* q, const uint8_t* t,
                  const KParams* kp, bsw_result* out, bsw_diag* diag,
-                 uint32_t* tile_ctr, const Status* st, hipStream_t s) {
+                 uint32_t* tile_ctr, const Status* st, uint32_t* qtiles,
+                 PairDesc* ovf, Status* stw, int ring, bool sym,
+                 unsigned long long* cls_cells, hipStream_t s) {
   const int wpb = lane_waves_per_block(cls);
-  const size_t lds = lane_lds_per_wave(cls) * wpb;
-  hipLaunchKernelGGL(lane_fn(cls, persist), dim3(blocks), dim3(wpb * 64), lds, s,
-                     desc, cls_range, cls, q, t, kp, out, diag, tile_ctr, st);
+  if (cls < CLS_W16)
+    hipLaunchKernelGGL(lane8_fn(cls, sym), dim3(blocks), dim3(64), (size_t)ring * 512, s,
+                       desc, range, q, t, kp, out, diag, tile_ctr, st, qtiles, ovf, stw,
+                       persist ? 1 : 0, ring, cls_cells);
+  else
+    hipLaunchKernelGGL(lanew_fn(cls, persist), dim3(blocks), dim3(wpb * 64),
+                       lane_lds_per_wave(cls) * wpb, s, desc, range, q, t, kp, out, diag,
+                       tile_ctr, st, cls_cells);
 }
 
-void launch_long(const PairDesc* desc, const int64_t* cls_range, const uint8_t* q,
+void launch_long(const PairDesc* desc, const long long* range, const uint8_t* q,
                  const uint8_t* t, const KParams* kp, bsw_result* out,
                  bsw_diag* diag, uint32_t* ctr, int2* gbuf, uint8_t* gq,
-                 const Status* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_long, dim3(LONG_SLOTS), dim3(64), 0, s, desc, cls_range, q, t,
-                     kp, out, diag, ctr, gbuf, gq, st);
+                 const Status* st, unsigned long long* cls_cells, hipStream_t s) {
+  hipLaunchKernelGGL(k_long, dim3(LONG_SLOTS), dim3(64), 0, s, desc, range, q, t,
+                     kp, out, diag, ctr, gbuf, gq, st, cls_cells);
 }
 
 }  // namespace bsw

@@ -164,3 +164,28 @@ def test_invalid_pairs_rejected(ctx, bsw):
 def test_empty_batch(ctx):
     b = synth.from_pairs([], [synth.BWA_DEFAULT])
     assert len(ctx.extend(b)) == 0
+
+
+def test_eight_bit_speculation_boundaries(oracle_lib, ctx):
+    """Pairs whose score bound exceeds 8 bits start in 8-bit records and are
+    rerun with 16-bit records when their best score shows a stored value may
+    have overflowed.  Scores straddling 255, seeds near 255, and a scoring
+    whose match exceeds the gap-open cost (so E can exceed the best score)
+    must all come out exact."""
+    rng = np.random.default_rng(31)
+    scs = [synth.BWA_DEFAULT, synth.scoring(match=5, mismatch=-2, o=0, e=1),
+           synth.scoring(match=3, mismatch=-1, o=1, e=1, w=40)]
+    pairs, pids = [], []
+    for _ in range(6000):
+        L = int(rng.integers(1, 257))
+        q = rng.integers(0, 4, L)
+        keep = int(rng.integers(0, L + 1))
+        t = np.concatenate([q[:keep], rng.integers(0, 5, int(rng.integers(0, 80)))])
+        h0 = int(rng.choice([int(rng.integers(1, 60)), int(rng.integers(150, 300))]))
+        pairs.append((q, t, h0))
+        pids.append(int(rng.integers(0, len(scs))))
+    b = synth.from_pairs(pairs, scs, param_id=pids)
+    want, wdiag = oracle_run(oracle_lib, b)
+    got, gdiag = ctx.extend(b, with_diag=True)
+    assert_same(got, want, gdiag, wdiag, "speculation")
+    assert (want["score"] > 255).sum() > 500  # the rerun path is exercised
