@@ -27,10 +27,10 @@ int lane_blocks_per_cu(int cls, bool persist, size_t lds);
 int lane8_ring_chunks(int cls, int wmax);
 size_t lane8_qtile_words(int cls);
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
-void launch_prep(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
-                 const int32_t* h0, const uint8_t* pid, int n_params,
-                 const KParams* kp, int min_bits, int force_mode, uint32_t* keys,
-                 uint32_t* hist, Status* st, hipStream_t s);
+void launch_prep(int64_t n, const uint8_t* q, const uint8_t* t, const uint64_t* q_off,
+                 const uint64_t* t_off, const int32_t* h0, const uint8_t* pid,
+                 int n_params, const KParams* kp, int min_bits, int force_mode,
+                 uint32_t* keys, uint32_t* hist, Status* st, hipStream_t s);
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
                   hipStream_t s);
 void launch_scan(const uint32_t* hist, uint32_t* cursor, long long* cls_range,
@@ -184,9 +184,16 @@ struct bsw_ctx {
   hipStream_t stream = nullptr;
   // ev[0] start, ev[1] binning done, ev[2] before the DP kernels, ev[3] end
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  // one event after each DP launch, and what each launch ran
+  // start and end events of each DP launch (on the launch's stream), and
+  // what each launch ran
   static constexpr int MAXL = NCLS + 2;
   hipEvent_t lev[MAXL] = {};
+  hipEvent_t lev0[MAXL] = {};
+  // side streams of the batched path: classes run concurrently
+  static constexpr int NSIDE = 4;
+  hipStream_t side[NSIDE] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[NSIDE] = {};
   int lcls[MAXL] = {};
   int n_launch = 0;
   double lms[MAXL] = {};
@@ -246,7 +253,7 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipEventRecord(c->ev[0], s));
   launch_fill((uint32_t*)(base + L.zero_beg), (int64_t)((L.zero_end - L.zero_beg) / 4), s);
-  launch_prep(n, q_off, t_off, h0, pid, n_params, c->d_kp, c->opts.min_lane_bits,
+  launch_prep(n, q, t, q_off, t_off, h0, pid, n_params, c->d_kp, c->opts.min_lane_bits,
               c->opts.force_mode, keys, hist, st, s);
   launch_codes(q, q_off, n, st, s);
   launch_codes(t, t_off, n, st, s);
@@ -293,19 +300,44 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
   c->n_dp_launches = 0;
   c->n_launch = 0;
   HIPCHK(hipEventRecord(c->ev[2], s));
-  auto mark = [&](int cls) -> int {
+  // launch bracketing: start/end events on the launch's stream
+  auto begin_launch = [&](int cls, hipStream_t ls) -> int {
     c->lcls[c->n_launch] = cls;
-    HIPCHK(hipEventRecord(c->lev[c->n_launch], s));
+    HIPCHK(hipEventRecord(c->lev0[c->n_launch], ls));
+    return BSW_OK;
+  };
+  auto end_launch = [&](hipStream_t ls) -> int {
+    HIPCHK(hipEventRecord(c->lev[c->n_launch], ls));
     ++c->n_launch;
     ++c->n_dp_launches;
     return BSW_OK;
   };
-  for (int cls = 0; cls < CLS_LONG; ++cls) {
+  // batched path: the classes run concurrently on side streams, widest
+  // first, so that one class's tail overlaps the next class's work; the
+  // 16-bit rerun waits for all of them.  Plain path: one stream, in order.
+  int nside_used = 0;
+  if (persist) {
+    HIPCHK(hipEventRecord(c->fork_ev, s));
+    for (int k = 0; k < bsw_ctx::NSIDE; ++k) HIPCHK(hipStreamWaitEvent(c->side[k], c->fork_ev, 0));
+  }
+  int order[NCLS], no = 0;
+  for (int cls = CLS_W16 - 1; cls >= CLS_L8; --cls) order[no++] = cls;   // 8-bit, widest first
+  for (int cls = CLS_W16; cls < CLS_LONG; ++cls) order[no++] = cls;
+  for (int oi = 0; oi < no; ++oi) {
+    const int cls = order[oi];
     if (blocks[cls] <= 0) continue;
+    hipStream_t ls = persist ? c->side[nside_used++ % bsw_ctx::NSIDE] : s;
+    if ((rc = begin_launch(cls, ls))) return rc;
     launch_lane(cls, persist, (unsigned)blocks[cls], desc, cls_range + 2 * cls, q, t,
                 c->d_kp, out, diag, ctr + cls, st, qt ? qt + qt_off[cls] : nullptr, ovf,
-                st, ring[cls], sym, &st->cls_cells[cls], s);
-    if ((rc = mark(cls))) return rc;
+                st, ring[cls], sym, &st->cls_cells[cls], ls);
+    if ((rc = end_launch(ls))) return rc;
+  }
+  if (persist) {
+    for (int k = 0; k < bsw_ctx::NSIDE; ++k) {
+      HIPCHK(hipEventRecord(c->join_ev[k], c->side[k]));
+      HIPCHK(hipStreamWaitEvent(s, c->join_ev[k], 0));
+    }
   }
   if (c->h_cls[2 * CLS_LONG + 1] > 0) {
     const size_t need = (size_t)LONG_SLOTS * LONG_SLOT_COLS * (sizeof(int2) + 1);
@@ -313,18 +345,20 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
     if (rc) return rc;
     int2* gbuf = (int2*)c->longbuf.p;
     uint8_t* gq = (uint8_t*)(gbuf + (size_t)LONG_SLOTS * LONG_SLOT_COLS);
+    if ((rc = begin_launch(CLS_LONG, s))) return rc;
     launch_long(desc, cls_range + 2 * CLS_LONG, q, t, c->d_kp, out, diag, ctr + CLS_LONG,
                 gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
-    if ((rc = mark(CLS_LONG))) return rc;
+    if ((rc = end_launch(s))) return rc;
   }
   if (any8) {
     // 16-bit rerun of the pairs the 8-bit kernels could not settle; the
     // count is only known on the device, so the grid is persistent
     const int rcls = CLS_W16 + NLW - 1;
+    if ((rc = begin_launch(NCLS, s))) return rc;
     launch_lane(rcls, true, (unsigned)(c->blocks_per_cu[1][rcls] * c->num_cu), ovf,
                 st->ovf_range, q, t, c->d_kp, out, diag, ctr + NCLS, st, nullptr, nullptr,
                 st, 0, false, &st->cls_cells[NCLS], s);
-    if ((rc = mark(NCLS))) return rc;
+    if ((rc = end_launch(s))) return rc;
   }
   HIPCHK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
   HIPCHK(hipGetLastError());
@@ -343,13 +377,11 @@ void record_timing(bsw_ctx* c) {
     c->timing[2] = b;
     c->timing[3] = c->n_dp_launches;
   }
-  hipEvent_t prev = c->ev[2];
   for (int k = 0; k < c->n_launch; ++k) {
     float ms = 0;
-    if (hipEventElapsedTime(&ms, prev, c->lev[k]) != hipSuccess) ms = 0;
+    if (hipEventElapsedTime(&ms, c->lev0[k], c->lev[k]) != hipSuccess) ms = 0;
     c->lms[k] = ms;
     c->lcells[k] = c->h_status->cls_cells[c->lcls[k]];
-    prev = c->lev[k];
   }
 }
 
@@ -397,6 +429,14 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
     if (hipEventCreate(&e) != hipSuccess) rc = BSW_EDEVICE;
   for (auto& e : c->lev)
     if (hipEventCreate(&e) != hipSuccess) rc = BSW_EDEVICE;
+  for (auto& e : c->lev0)
+    if (hipEventCreate(&e) != hipSuccess) rc = BSW_EDEVICE;
+  for (auto& e : c->join_ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = BSW_EDEVICE;
+  if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess)
+    rc = BSW_EDEVICE;
+  for (auto& st : c->side)
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) rc = BSW_EDEVICE;
   if (hipHostMalloc((void**)&c->h_kp, sizeof(KParams) * 256, 0) != hipSuccess ||
       hipHostMalloc((void**)&c->h_status, sizeof(Status), 0) != hipSuccess ||
       hipHostMalloc((void**)&c->h_cls, sizeof(int64_t) * 2 * NCLS, 0) != hipSuccess ||
@@ -435,6 +475,13 @@ void bsw_ctx_destroy(bsw_ctx* c) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->lev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->lev0)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->join_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  for (auto& st : c->side)
+    if (st) (void)hipStreamDestroy(st);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

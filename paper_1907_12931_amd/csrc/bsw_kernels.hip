@@ -96,7 +96,9 @@ __global__ void k_fill(uint32_t* p, int64_t nwords) {
     p[i] = 0;
 }
 
-__global__ void k_prep(int64_t n, const uint64_t* __restrict__ q_off,
+__global__ void k_prep(int64_t n, const uint8_t* __restrict__ q,
+                       const uint8_t* __restrict__ t,
+                       const uint64_t* __restrict__ q_off,
                        const uint64_t* __restrict__ t_off,
                        const int32_t* __restrict__ h0,
                        const uint8_t* __restrict__ pid, int n_params,
@@ -145,9 +147,30 @@ __global__ void k_prep(int64_t n, const uint64_t* __restrict__ q_off,
       cls = (wd == W16 ? CLS_W16 : CLS_W32) + c;
       cap = LW_CAP[c];
     }
-    // longest first inside a class: larger query, then larger target
+    // longest first inside a class: larger query first, then more rows.
+    // For wide queries the rows are estimated by walking the main
+    // diagonal without gaps until its score drops below zero or more than
+    // z-drop below its running maximum: pairs that end early (diverged or
+    // dropping) then share tiles, so the lanes of a tile finish together.
+    int rows_est = tl;
+    if (ql > 192 && ql <= 256) {
+      const uint8_t* qs = q + qo;
+      const uint8_t* tt = t + to;
+      const int L = ql < tl ? ql : tl;
+      int sc = hh, mx = hh;
+      for (int j = 0; j < L; ++j) {
+        const int a = tt[j], b = qs[j];
+        sc += (int)(int8_t)(__builtin_amdgcn_perm(P.prow[a < 5 ? a : 0][1],
+                                                  P.prow[a < 5 ? a : 0][0], b) & 0xffu);
+        mx = sc > mx ? sc : mx;
+        if (sc <= 0 || (P.zdrop > 0 && mx - sc > P.zdrop)) {
+          rows_est = j + 1;
+          break;
+        }
+      }
+    }
     int qq = (int)((int64_t)ql * 64 / (cap + 1));
-    int tq = tl >> 4;
+    int tq = rows_est >> 4;
     qq = qq > 63 ? 63 : qq;
     tq = tq > 63 ? 63 : tq;
     const uint32_t key = ((uint32_t)cls << KEY_SUB_BITS) |
@@ -487,7 +510,8 @@ __device__ __forceinline__ int wave_max(int v) {
 // is ever read again, so with 4*RC > 2w' + 4 no live column shares a
 // slot with another live column.  Columns are initialised lazily (first-
 // row value of Eq. (3)) the first time the band end reaches them.  With
-// RC = CAP/4 + 1 the ring never wraps.
+// RC = CAP/4 + 1 the ring never wraps.  The host keeps 2*RC > CAP/4, so
+// a chunk index (at most CAP/4) needs at most one subtraction.
 __device__ __forceinline__ int ring_slot(int chunk, int rc) {
   return chunk >= rc ? chunk - rc : chunk;
 }
@@ -504,7 +528,7 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
   if (st->bad) return;
   extern __shared__ __align__(16) uint2 rb[];  // [RC][64]
   const int lane = threadIdx.x;
-  uint32_t* qt = qtiles + (size_t)blockIdx.x * (CAP / 4 + 2) * 64 + lane;
+  uint32_t* qt = qtiles + (size_t)blockIdx.x * (CAP / 4 + 3) * 64 + lane;
   uint2* my = rb + lane;
   unsigned char* myb = (unsigned char*)(rb + lane);  // byte view, stride 512
   // byte address of column x's (H, E) pair in this lane's ring
@@ -579,10 +603,27 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
     long long cells = 0;
     bool live = valid && Lt > 0;
     const uint8_t* ts = t + pd.to;
-    int tb_next = live ? ts[0] : 0;
+    // target codes of rows i..i+3 packed in tq; b0..b3 hold rows i+4..i+7,
+    // loaded four rows before they are packed
+    uint32_t tq = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    if (live) {
+      b0 = ts[0];
+      if (1 < Lt) b1 = ts[1];
+      if (2 < Lt) b2 = ts[2];
+      if (3 < Lt) b3 = ts[3];
+    }
     for (int i = 0;; ++i) {
       live = live && i < Lt;
       if (__ballot(live) == 0) break;
+      if ((i & 3) == 0) {
+        tq = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+        if (live) {
+          if (i + 4 < Lt) b0 = ts[i + 4];
+          if (i + 5 < Lt) b1 = ts[i + 5];
+          if (i + 6 < Lt) b2 = ts[i + 6];
+          if (i + 7 < Lt) b3 = ts[i + 7];
+        }
+      }
       int hl = 0, f = 0;
       uint32_t lo = 0, hi = 0;
       if (live) {
@@ -601,8 +642,7 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
           ++hw;
           *(unsigned short*)COL(hw) = (unsigned short)imax(0, h0 - oI - eI * hw);
         }
-        const int tb = tb_next;
-        tb_next = i + 1 < Lt ? ts[i + 1] : 0;
+        const int tb = (tq >> (8 * (i & 3))) & 0xff;
         lo = pl[0];
         hi = ph[0];
 #pragma unroll
@@ -622,27 +662,53 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
       int mkey = 0;
       int c = c0;
       if (c < cf) {
-        int sl = ring_slot(c, RC);
-        uint2 ch = my[sl * 64];
-        uint32_t q0 = qt[c * 64], q1 = qt[(c + 1) * 64];
-        for (; c < cf; ++c) {
-          int sn = sl + 1;
-          sn = sn == RC ? 0 : sn;
-          // next chunk's buffer word and the query two chunks ahead
-          const uint2 chn = my[sn * 64];
-          const uint32_t q2 = qt[(c + 2) * 64];
-          const uint32_t sc = __builtin_amdgcn_perm(hi, lo, q0);
+        // two chunks per step, A = chunk c and B = chunk c+1; each load is
+        // issued right after its register is last used and consumed in the
+        // next step, so LDS and L2 latency overlap a whole step of work
+        int sa = ring_slot(c, RC);
+        int sb = sa + 1 == RC ? 0 : sa + 1;
+        uint2 chA = my[sa * 64], chB = my[sb * 64];
+        uint32_t qA = qt[c * 64], qB = qt[(c + 1) * 64];
+        for (; c + 2 <= cf; c += 2) {
+          int sa2 = sb + 1 == RC ? 0 : sb + 1;
+          int sb2 = sa2 + 1 == RC ? 0 : sa2 + 1;
+          {
+            const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qA);
+            qA = qt[(c + 2) * 64];
+            const int j0 = 4 * c;
+            uint32_t n0 = 0, n1 = 0;
+            BSW_CELL8(chA.x, 0, sc, 0, j0, n0, 0);
+            BSW_CELL8(chA.x, 16, sc, 1, j0 + 1, n0, 16);
+            BSW_CELL8(chA.y, 0, sc, 2, j0 + 2, n1, 0);
+            BSW_CELL8(chA.y, 16, sc, 3, j0 + 3, n1, 16);
+            my[sa * 64] = make_uint2(n0, n1);
+            chA = my[sa2 * 64];
+          }
+          {
+            const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qB);
+            qB = qt[(c + 3) * 64];
+            const int j0 = 4 * c + 4;
+            uint32_t n0 = 0, n1 = 0;
+            BSW_CELL8(chB.x, 0, sc, 0, j0, n0, 0);
+            BSW_CELL8(chB.x, 16, sc, 1, j0 + 1, n0, 16);
+            BSW_CELL8(chB.y, 0, sc, 2, j0 + 2, n1, 0);
+            BSW_CELL8(chB.y, 16, sc, 3, j0 + 3, n1, 16);
+            my[sb * 64] = make_uint2(n0, n1);
+            chB = my[sb2 * 64];
+          }
+          sa = sa2;
+          sb = sb2;
+        }
+        if (c < cf) {
+          const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qA);
           const int j0 = 4 * c;
           uint32_t n0 = 0, n1 = 0;
-          BSW_CELL8(ch.x, 0, sc, 0, j0, n0, 0);
-          BSW_CELL8(ch.x, 16, sc, 1, j0 + 1, n0, 16);
-          BSW_CELL8(ch.y, 0, sc, 2, j0 + 2, n1, 0);
-          BSW_CELL8(ch.y, 16, sc, 3, j0 + 3, n1, 16);
-          my[sl * 64] = make_uint2(n0, n1);
-          sl = sn;
-          ch = chn;
-          q0 = q1;
-          q1 = q2;
+          BSW_CELL8(chA.x, 0, sc, 0, j0, n0, 0);
+          BSW_CELL8(chA.x, 16, sc, 1, j0 + 1, n0, 16);
+          BSW_CELL8(chA.y, 0, sc, 2, j0 + 2, n1, 0);
+          BSW_CELL8(chA.y, 16, sc, 3, j0 + 3, n1, 16);
+          my[sa * 64] = make_uint2(n0, n1);
+          ++c;
         }
       }
       for (; c < c1; ++c) {
@@ -843,15 +909,19 @@ int lane_blocks_per_cu(int cls, bool persist, size_t lds) {
   return nb < 1 ? 1 : nb;
 }
 
-// ring chunks of an 8-bit class for band half-widths up to wmax
+// ring chunks of an 8-bit class for band half-widths up to wmax: enough
+// for the live band (4*RC > 2w' + 4, plus a spare chunk), and at least half
+// of the chunks a query of the class can touch, so that one conditional
+// subtraction maps every chunk index (at most full - 1) into the ring
 int lane8_ring_chunks(int cls, int wmax) {
   const int full = cls_cap(cls) / 4 + 1;
-  const long long need = (2LL * wmax + 5 + 3) / 4 + 1;
+  long long need = (2LL * wmax + 5 + 3) / 4 + 1;
+  if (need < (full + 1) / 2) need = (full + 1) / 2;
   return need >= full ? full : (int)need;
 }
 
 // HBM words of query tile per workgroup of an 8-bit class
-size_t lane8_qtile_words(int cls) { return ((size_t)cls_cap(cls) / 4 + 2) * 64; }
+size_t lane8_qtile_words(int cls) { return ((size_t)cls_cap(cls) / 4 + 3) * 64; }
 
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s) {
   int64_t blocks = (nwords + 255) / 256;
@@ -860,13 +930,13 @@ void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, nwords);
 }
 
-void launch_prep(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
-                 const int32_t* h0, const uint8_t* pid, int n_params,
-                 const KParams* kp, int min_bits, int force_mode, uint32_t* keys,
-                 uint32_t* hist, Status* st, hipStream_t s) {
+void launch_prep(int64_t n, const uint8_t* q, const uint8_t* t, const uint64_t* q_off,
+                 const uint64_t* t_off, const int32_t* h0, const uint8_t* pid,
+                 int n_params, const KParams* kp, int min_bits, int force_mode,
+                 uint32_t* keys, uint32_t* hist, Status* st, hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)blocks), dim3(256), 0, s, n, q_off,
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)blocks), dim3(256), 0, s, n, q, t, q_off,
                      t_off, h0, pid, n_params, kp, min_bits, force_mode, keys, hist, st);
 }
 

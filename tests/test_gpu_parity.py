@@ -189,3 +189,20 @@ def test_eight_bit_speculation_boundaries(oracle_lib, ctx):
     got, gdiag = ctx.extend(b, with_diag=True)
     assert_same(got, want, gdiag, wdiag, "speculation")
     assert (want["score"] > 255).sum() > 500  # the rerun path is exercised
+
+
+@pytest.mark.parametrize("w,zdrop,asym", [(3, 0, False), (20, 30, False), (40, 60, True),
+                                           (7, 0, True)])
+def test_narrow_bands_long_queries(oracle_lib, ctx, w, zdrop, asym):
+    """Long queries with narrow bands: the 8-bit kernels keep the row buffer
+    in a ring sized from w; the ring must never alias a live column, for
+    symmetric and asymmetric gap costs."""
+    b = synth.batched_mix(n=30_000, seed=40 + w)
+    ql = np.diff(b["q_off"].astype(np.int64))
+    b = synth.subset(b, np.nonzero(ql > 96)[0])
+    sc = (synth.scoring(match=2, mismatch=-3, o=4, e=2, o_ins=7, e_ins=1, w=w, zdrop=zdrop)
+          if asym else synth.scoring(w=w, zdrop=zdrop))
+    b["scorings"] = [sc]
+    want, wdiag = oracle_run(oracle_lib, b)
+    got, gdiag = ctx.extend(b, with_diag=True)
+    assert_same(got, want, gdiag, wdiag, f"narrow w={w}")
