@@ -26,6 +26,7 @@ hipError_t lane_setup(int cls, bool persist);
 int lane_blocks_per_cu(int cls, bool persist, size_t lds);
 int lane8_ring_chunks(int cls, int wmax);
 size_t lane8_qtile_words(int cls);
+size_t lane_chunk_row_bytes(int cls);
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
 void launch_prep(int64_t n, const uint8_t* q, const uint8_t* t, const uint64_t* q_off,
                  const uint64_t* t_off, const int32_t* h0, const uint8_t* pid,
@@ -43,7 +44,7 @@ void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
                  const long long* range, const uint8_t* q, const uint8_t* t,
                  const KParams* kp, bsw_result* out, bsw_diag* diag,
                  uint32_t* tile_ctr, const Status* st, uint32_t* qtiles,
-                 PairDesc* ovf, Status* stw, int ring, bool sym,
+                 PairDesc* ovf, long long* ovf_count, int ring, bool sym,
                  unsigned long long* cls_cells, hipStream_t s);
 void launch_long(const PairDesc* desc, const long long* range, const uint8_t* q,
                  const uint8_t* t, const KParams* kp, bsw_result* out,
@@ -103,10 +104,11 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up for n pairs.
 struct Layout {
-  size_t keys, desc, ovf, hist, cursor, cls_range, status, ctr, zero_beg, zero_end, total;
+  size_t keys, desc, ovf, ovf2, hist, cursor, cls_range, status, ctr, zero_beg, zero_end,
+      total;
 };
 
-constexpr int NCTR = NCLS + 2;  // one tile counter per class, the rerun, spare
+constexpr int NCTR = NCLS + 3;  // one tile counter per class, two reruns, spare
 
 Layout layout_for(int64_t n) {
   Layout L;
@@ -129,6 +131,8 @@ Layout layout_for(int64_t n) {
   L.desc = o;
   o = align_up(o + (size_t)n * sizeof(PairDesc), 256);
   L.ovf = o;
+  o = align_up(o + (size_t)n * sizeof(PairDesc), 256);
+  L.ovf2 = o;
   o = align_up(o + (size_t)n * sizeof(PairDesc), 256);
   L.total = o;
   return L;
@@ -186,7 +190,7 @@ struct bsw_ctx {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // start and end events of each DP launch (on the launch's stream), and
   // what each launch ran
-  static constexpr int MAXL = NCLS + 2;
+  static constexpr int MAXL = NCLS + 3;
   hipEvent_t lev[MAXL] = {};
   hipEvent_t lev0[MAXL] = {};
   // side streams of the batched path: classes run concurrently
@@ -208,8 +212,8 @@ struct bsw_ctx {
   Status* h_status = nullptr;  // pinned
   long long* h_cls = nullptr;  // pinned [NCLS][2]
   int blocks_per_cu[2][NCLS] = {};
-  // occupancy of the 8-bit classes by (symmetric variant, ring chunks)
-  int occ8[2][NL8][80] = {};
+  // occupancy of the chunked classes by (symmetric variant, ring chunks)
+  int occc[2][NCLS][80] = {};
   int last_status = BSW_OK;
   bool pending = false;
   hipStream_t pending_stream = nullptr;
@@ -246,6 +250,7 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
   uint32_t* cursor = (uint32_t*)(base + L.cursor);
   long long* cls_range = (long long*)(base + L.cls_range);
   PairDesc* ovf = (PairDesc*)(base + L.ovf);
+  PairDesc* ovf2 = (PairDesc*)(base + L.ovf2);
   uint32_t* keys = (uint32_t*)(base + L.keys);
   PairDesc* desc = (PairDesc*)(base + L.desc);
 
@@ -270,11 +275,19 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
                 ~(unsigned long long)c->h_status->first_bad_inv);
 
   const bool persist = c->opts.path != BSW_PATH_PLAIN;
-  // grid of every lane class, and the query-tile space of the 8-bit ones
+  // occupancy of a chunked class with a given ring (cached per context)
+  auto chunked_per_cu = [&](int cls, int rg) {
+    int& occ = c->occc[sym ? 1 : 0][cls][rg];
+    if (!occ) occ = lane_blocks_per_cu(cls, sym, (size_t)rg * lane_chunk_row_bytes(cls));
+    return occ;
+  };
+  // grid of every lane class, and the query-tile space of the chunked ones;
+  // the 16-bit rerun of 8-bit overflows gets the last query-tile region
+  const int r1cls = CLS_W16 + NLW - 1, r2cls = CLS_W32 + NLW - 1;
   int64_t blocks[NCLS] = {};
   int ring[NCLS] = {};
   size_t qt_off[NCLS] = {}, qt_words = 0;
-  bool any8 = false;
+  bool any8 = false, any16 = false;
   for (int cls = 0; cls < CLS_LONG; ++cls) {
     const int64_t count = c->h_cls[2 * cls + 1];
     if (count <= 0) continue;
@@ -282,19 +295,21 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
     const int64_t tiles = (count + 63) / 64;
     blocks[cls] = (tiles + wpb - 1) / wpb;
     int per_cu = c->blocks_per_cu[1][cls];
-    if (cls < CLS_W16) {
+    if (cls < CLS_W32) {
       ring[cls] = lane8_ring_chunks(cls, wmax);
-      int& occ = c->occ8[sym ? 1 : 0][cls - CLS_L8][ring[cls]];
-      if (!occ) occ = lane_blocks_per_cu(cls, sym, (size_t)ring[cls] * 512);
-      per_cu = occ;
+      per_cu = chunked_per_cu(cls, ring[cls]);
     }
     if (persist) blocks[cls] = std::min(blocks[cls], (int64_t)per_cu * c->num_cu);
-    if (cls < CLS_W16) {
-      any8 = true;
+    if (cls < CLS_W32) {
+      (cls < CLS_W16 ? any8 : any16) = true;
       qt_off[cls] = qt_words;
       qt_words += (size_t)blocks[cls] * lane8_qtile_words(cls);
     }
   }
+  const int r1ring = lane8_ring_chunks(r1cls, wmax);
+  const int64_t r1blocks = any8 ? (int64_t)chunked_per_cu(r1cls, r1ring) * c->num_cu : 0;
+  const size_t r1qt = qt_words;
+  qt_words += (size_t)r1blocks * lane8_qtile_words(r1cls);
   if (qt_words && (rc = c->qtiles.ensure(qt_words * 4))) return rc;
   uint32_t* qt = (uint32_t*)c->qtiles.p;
   c->n_dp_launches = 0;
@@ -314,7 +329,7 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
   };
   // batched path: the classes run concurrently on side streams, widest
   // first, so that one class's tail overlaps the next class's work; the
-  // 16-bit rerun waits for all of them.  Plain path: one stream, in order.
+  // reruns wait for all of them.  Plain path: one stream, in order.
   int nside_used = 0;
   if (persist) {
     HIPCHK(hipEventRecord(c->fork_ev, s));
@@ -328,9 +343,12 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
     if (blocks[cls] <= 0) continue;
     hipStream_t ls = persist ? c->side[nside_used++ % bsw_ctx::NSIDE] : s;
     if ((rc = begin_launch(cls, ls))) return rc;
+    // 8-bit overflows go to the first rerun list, 16-bit ones to the second
     launch_lane(cls, persist, (unsigned)blocks[cls], desc, cls_range + 2 * cls, q, t,
-                c->d_kp, out, diag, ctr + cls, st, qt ? qt + qt_off[cls] : nullptr, ovf,
-                st, ring[cls], sym, &st->cls_cells[cls], ls);
+                c->d_kp, out, diag, ctr + cls, st, qt ? qt + qt_off[cls] : nullptr,
+                cls < CLS_W16 ? ovf : ovf2,
+                cls < CLS_W16 ? &st->ovf_range[1] : &st->ovf2_range[1], ring[cls], sym,
+                &st->cls_cells[cls], ls);
     if ((rc = end_launch(ls))) return rc;
   }
   if (persist) {
@@ -350,14 +368,22 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
                 gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
     if ((rc = end_launch(s))) return rc;
   }
+  // reruns: the counts are only known on the device, so the grids are
+  // persistent and exit at once when their list is empty
   if (any8) {
-    // 16-bit rerun of the pairs the 8-bit kernels could not settle; the
-    // count is only known on the device, so the grid is persistent
-    const int rcls = CLS_W16 + NLW - 1;
+    // 16-bit chunked rerun of the pairs the 8-bit kernels could not settle
     if ((rc = begin_launch(NCLS, s))) return rc;
-    launch_lane(rcls, true, (unsigned)(c->blocks_per_cu[1][rcls] * c->num_cu), ovf,
-                st->ovf_range, q, t, c->d_kp, out, diag, ctr + NCLS, st, nullptr, nullptr,
-                st, 0, false, &st->cls_cells[NCLS], s);
+    launch_lane(r1cls, true, (unsigned)r1blocks, ovf, st->ovf_range, q, t, c->d_kp, out,
+                diag, ctr + NCLS, st, qt + r1qt, ovf2, &st->ovf2_range[1], r1ring, sym,
+                &st->cls_cells[NCLS], s);
+    if ((rc = end_launch(s))) return rc;
+  }
+  if (any8 || any16) {
+    // 32-bit rerun of the pairs the 16-bit kernels could not settle
+    if ((rc = begin_launch(NCLS + 1, s))) return rc;
+    launch_lane(r2cls, true, (unsigned)(c->blocks_per_cu[1][r2cls] * c->num_cu), ovf2,
+                st->ovf2_range, q, t, c->d_kp, out, diag, ctr + NCLS + 1, st, nullptr,
+                nullptr, nullptr, 0, false, &st->cls_cells[NCLS + 1], s);
     if ((rc = end_launch(s))) return rc;
   }
   HIPCHK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
@@ -536,12 +562,12 @@ int bsw_ctx_last_kernels(bsw_ctx* c, int32_t* cls, int64_t* cells, double* ms,
 }
 
 const char* bsw_class_name(int32_t cls) {
-  static const char* names[NCLS + 1] = {
+  static const char* names[NCLS + 2] = {
       "lane8_q32",  "lane8_q64",  "lane8_q96",  "lane8_q128", "lane8_q160",
       "lane8_q192", "lane8_q224", "lane8_q256", "lane16_q32", "lane16_q64",
       "lane16_q128", "lane16_q256", "lane32_q32", "lane32_q64", "lane32_q128",
-      "lane32_q256", "long", "rerun16"};
-  return cls >= 0 && cls <= NCLS ? names[cls] : "?";
+      "lane32_q256", "long", "rerun16", "rerun32"};
+  return cls >= 0 && cls <= NCLS + 1 ? names[cls] : "?";
 }
 
 int bsw_ctx_last_timing(bsw_ctx* c, double out4[4]) {

@@ -34,8 +34,12 @@ struct KParams {
 //    speculatively: its final best score tells whether any stored value can
 //    have exceeded 8 bits (best + max(0, A - o_del - e_del) > 255), and
 //    such pairs are run again with 16-bit records.
-//  * W16 / W32 classes: 16- or 32-bit records for pairs whose bound (or a
-//    forced minimum width) needs them, and for the 8-bit overflow reruns.
+//  * W16 classes: 16-bit records, same chunked kernel, for pairs whose
+//    bound (or a forced minimum width) needs them; the 8-bit overflow
+//    reruns use the widest of them.
+//  * W32 classes: 32-bit records (one-lane-per-pair kernel with a private
+//    row buffer in LDS) for bounds over 16 bits, a forced 32-bit width and
+//    the (rare) 16-bit overflow reruns.
 //  * LONG: queries longer than 256.
 enum { W8 = 0, W16 = 1, W32 = 2 };
 enum { NL8 = 8, NLW = 4 };
@@ -59,6 +63,7 @@ struct Status {
   unsigned long long first_bad_inv;  // ~(smallest bad pair index); 0 = none
   unsigned long long long_max;   // largest query length in the long class
   long long ovf_range[2];        // {0, number of 8-bit overflow reruns}
+  long long ovf2_range[2];       // {0, number of 16-bit overflow reruns}
   unsigned long long cls_cells[32];  // band cells per class (+ rerun slot)
 };
 

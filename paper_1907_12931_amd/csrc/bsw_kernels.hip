@@ -149,19 +149,20 @@ __global__ void k_prep(int64_t n, const uint8_t* __restrict__ q,
     }
     // longest first inside a class: larger query first, then more rows.
     // For wide queries the rows are estimated by walking the main
-    // diagonal without gaps until its score drops below zero or more than
-    // z-drop below its running maximum: pairs that end early (diverged or
-    // dropping) then share tiles, so the lanes of a tile finish together.
+    // diagonal without gaps (every other position, counted twice) until its
+    // score drops below zero or more than z-drop below its running maximum:
+    // pairs that end early (diverged or dropping) then share tiles, so the
+    // lanes of a tile finish together.  Only the order depends on this.
     int rows_est = tl;
     if (ql > 192 && ql <= 256) {
       const uint8_t* qs = q + qo;
       const uint8_t* tt = t + to;
       const int L = ql < tl ? ql : tl;
       int sc = hh, mx = hh;
-      for (int j = 0; j < L; ++j) {
+      for (int j = 0; j < L; j += 2) {
         const int a = tt[j], b = qs[j];
-        sc += (int)(int8_t)(__builtin_amdgcn_perm(P.prow[a < 5 ? a : 0][1],
-                                                  P.prow[a < 5 ? a : 0][0], b) & 0xffu);
+        sc += 2 * (int)(int8_t)(__builtin_amdgcn_perm(P.prow[a < 5 ? a : 0][1],
+                                                      P.prow[a < 5 ? a : 0][0], b) & 0xffu);
         mx = sc > mx ? sc : mx;
         if (sc <= 0 || (P.zdrop > 0 && mx - sc > P.zdrop)) {
           rows_est = j + 1;
@@ -487,23 +488,85 @@ __device__ __forceinline__ int wave_max(int v) {
   return imax(imax(a, b), imax(c, d));
 }
 
-// One band cell of the 8-bit kernel on the byte pair (H, E) at bit offset
-// sh of word w, query score byte sb of sc; updates hl, f, mkey and writes
-// the new pair (H(i, j-1), E(i+1, j)) into nw.  Values above 255 only occur
-// in pairs that are rerun, so the packing does not mask them.
-#define BSW_CELL8(w, sh, sc, sb, j, nw, nsh)                                  \
-  {                                                                           \
-    const int d_ = ((w) >> (sh)) & 0xff;                                      \
-    const int e_ = ((w) >> ((sh) + 8)) & 0xff;                                \
-    const int s_ = (int)(int8_t)((sc) >> (8 * (sb)));                         \
-    const int M_ = d_ ? d_ + s_ : 0;                                          \
-    const int h_ = imax(imax(M_, e_), f);                                     \
-    const int en_ = imax(imax(e_ - eD, M_ - oeD), 0);                         \
-    nw |= ((uint32_t)hl | ((uint32_t)en_ << 8)) << (nsh);                     \
-    hl = h_;                                                                  \
-    mkey = imax(mkey, (int)(((uint32_t)h_ << 9) | (uint32_t)(j)));            \
-    f = imax(imax(f - eI, M_ - oeI), 0);                                      \
-  }
+// Chunk records of the chunked lane kernels: four consecutive columns of
+// one lane.  8-bit: an 8-byte word, bytes (H0,E0,H1,E1,H2,E2,H3,E3).
+// 16-bit: a 16-byte word, one 32-bit (H | E << 16) per column.
+template <int WB> struct Chunk;
+template <> struct Chunk<8> {
+  using T = uint2;
+  static constexpr int BYTES = 8;    // per lane per chunk
+  static constexpr int REC = 2;      // bytes per column record
+  static constexpr int MAXV = 255;
+  typedef unsigned short R;          // one column record
+};
+template <> struct Chunk<16> {
+  using T = uint4;
+  static constexpr int BYTES = 16;
+  static constexpr int REC = 4;
+  static constexpr int MAXV = 65535;
+  typedef uint32_t R;
+};
+
+// One band cell (Sec. 5.1 Eq. (2)): d = stored H(i-1, j-1), e = stored
+// E(i, j), s = S(t_i, q_j).  Updates hl (H(i, j-1) -> H(i, j)), f, mkey and
+// returns the new record (H(i, j-1), E(i+1, j)) unshifted (H in the low
+// field).  Values beyond the record width only occur in pairs that are
+// rerun wider, so the record is not masked.
+struct CellParams {
+  int eD, oeD, eI, oeI;
+};
+template <int WB>
+__device__ __forceinline__ uint32_t cell(int d, int e, int s, int j, int& hl, int& f,
+                                         int& mkey, const CellParams& cp) {
+  const int M = d ? d + s : 0;
+  const int h = imax(imax(M, e), f);
+  const int en = imax(imax(e - cp.eD, M - cp.oeD), 0);
+  const uint32_t r = (uint32_t)hl | ((uint32_t)en << WB);
+  hl = h;
+  mkey = imax(mkey, (int)(((uint32_t)h << 9) | (uint32_t)j));
+  f = imax(imax(f - cp.eI, M - cp.oeI), 0);
+  return r;
+}
+
+// the four cells of a whole chunk (no masking)
+__device__ __forceinline__ uint2 chunk_cells(const uint2 ch, uint32_t sc, int j0, int& hl,
+                                             int& f, int& mkey, const CellParams& cp) {
+  const uint32_t r0 = cell<8>(ch.x & 0xff, (ch.x >> 8) & 0xff, (int)(int8_t)sc, j0, hl, f,
+                              mkey, cp);
+  const uint32_t r1 = cell<8>((ch.x >> 16) & 0xff, ch.x >> 24, (int)(int8_t)(sc >> 8),
+                              j0 + 1, hl, f, mkey, cp);
+  const uint32_t r2 = cell<8>(ch.y & 0xff, (ch.y >> 8) & 0xff, (int)(int8_t)(sc >> 16),
+                              j0 + 2, hl, f, mkey, cp);
+  const uint32_t r3 = cell<8>((ch.y >> 16) & 0xff, ch.y >> 24, (int)(int8_t)(sc >> 24),
+                              j0 + 3, hl, f, mkey, cp);
+  return make_uint2(r0 | (r1 << 16), r2 | (r3 << 16));
+}
+__device__ __forceinline__ uint4 chunk_cells(const uint4 ch, uint32_t sc, int j0, int& hl,
+                                             int& f, int& mkey, const CellParams& cp) {
+  uint4 r;
+  r.x = cell<16>(ch.x & 0xffff, ch.x >> 16, (int)(int8_t)sc, j0, hl, f, mkey, cp);
+  r.y = cell<16>(ch.y & 0xffff, ch.y >> 16, (int)(int8_t)(sc >> 8), j0 + 1, hl, f, mkey, cp);
+  r.z = cell<16>(ch.z & 0xffff, ch.z >> 16, (int)(int8_t)(sc >> 16), j0 + 2, hl, f, mkey,
+                 cp);
+  r.w = cell<16>(ch.w & 0xffff, ch.w >> 16, (int)(int8_t)(sc >> 24), j0 + 3, hl, f, mkey,
+                 cp);
+  return r;
+}
+// column cc of a chunk, read and written as a record
+__device__ __forceinline__ uint32_t rec_get(const uint2& c, int cc) {
+  return ((cc < 2 ? c.x : c.y) >> (16 * (cc & 1))) & 0xffffu;
+}
+__device__ __forceinline__ void rec_set(uint2& c, int cc, uint32_t r) {
+  uint32_t& w = cc < 2 ? c.x : c.y;
+  const int sh = 16 * (cc & 1);
+  w = (w & ~(0xffffu << sh)) | ((r & 0xffffu) << sh);
+}
+__device__ __forceinline__ uint32_t rec_get(const uint4& c, int cc) {
+  return cc == 0 ? c.x : (cc == 1 ? c.y : (cc == 2 ? c.z : c.w));
+}
+__device__ __forceinline__ void rec_set(uint4& c, int cc, uint32_t r) {
+  if (cc == 0) c.x = r; else if (cc == 1) c.y = r; else if (cc == 2) c.z = r; else c.w = r;
+}
 
 // Row buffer in a ring of RC chunks: the band of row i lies in
 // [i - w', i + w' + 1] and nothing outside [beg, highest index written]
@@ -516,23 +579,40 @@ __device__ __forceinline__ int ring_slot(int chunk, int rc) {
   return chunk >= rc ? chunk - rc : chunk;
 }
 
-template <int CAP, bool SYM>
+// Lane mode with chunk records (the main kernel, 8- or 16-bit records).
+//
+// Every lane of the wave owns one pair; the wave walks rows in lock step
+// and, inside a row, walks the same column j in every lane (each lane masks
+// columns at or past its band end; columns left of its band start compute
+// zeros because the buffer there is kept at zero), so the row buffer can be
+// laid out column-major: chunk c of four columns for lane l is one record
+// word at [c][l], and the four query codes of a chunk are one dword at
+// [c][l] of a per-wave tile in HBM.  One LDS read, one LDS write, one
+// global read and one v_perm (four scores) serve four cells.
+//
+// A pair that may exceed the record width is detected from its final best
+// score (all stored H are <= best; stored E are <= best + max(0, A - o_del
+// - e_del)); it is then not written but queued (ovf) for a wider rerun.
+template <int CAP, bool SYM, int WB>
 __global__ void __launch_bounds__(64)
-k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
+k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
         const KParams* __restrict__ kp, bsw_result* __restrict__ out,
         bsw_diag* __restrict__ diag, uint32_t* tile_ctr, const Status* st,
         uint32_t* __restrict__ qtiles, PairDesc* __restrict__ ovf,
-        Status* __restrict__ stw, int persist, int RC,
+        long long* __restrict__ ovf_count, int persist, int RC,
         unsigned long long* __restrict__ cls_cells) {
   if (st->bad) return;
-  extern __shared__ __align__(16) uint2 rb[];  // [RC][64]
+  using CK = Chunk<WB>;
+  using T = typename CK::T;
+  using R = typename CK::R;
+  extern __shared__ __align__(16) unsigned char smem[];  // [RC][64] chunk words
   const int lane = threadIdx.x;
   uint32_t* qt = qtiles + (size_t)blockIdx.x * (CAP / 4 + 3) * 64 + lane;
-  uint2* my = rb + lane;
-  unsigned char* myb = (unsigned char*)(rb + lane);  // byte view, stride 512
-  // byte address of column x's (H, E) pair in this lane's ring
-#define COL(x) (myb + ring_slot((x) >> 2, RC) * 512 + ((x) & 3) * 2)
+  T* my = (T*)smem + lane;
+  unsigned char* myb = smem + lane * CK::BYTES;
+  // column x's (H, E) record in this lane's ring
+#define COL(x) (*(R*)(myb + ring_slot((x) >> 2, RC) * (64 * CK::BYTES) + ((x) & 3) * CK::REC))
   const long long begin = range[0], count = range[1];
   const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
   uint32_t tile = blockIdx.x;
@@ -559,7 +639,8 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
     const KParams& P = kp[pd.pid];
     const int Lq = pd.ql, Lt = valid ? pd.tl : 0, h0 = pd.h0;
     const int oD = P.o_del, eD = P.e_del, oI = P.o_ins, eI = P.e_ins;
-    const int oeD = P.oe_del, oeI = SYM ? P.oe_del : P.oe_ins, zd = P.zdrop;
+    const CellParams cp = {eD, P.oe_del, eI, SYM ? P.oe_del : P.oe_ins};
+    const int zd = P.zdrop;
     const int wb = band_cap(P, Lq);
     uint32_t pl[5], ph[5];
 #pragma unroll
@@ -571,15 +652,14 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
     // for the columns the ring holds at the start; the rest come lazily
     int hw = imin(Lq, 4 * RC - 1);  // highest initialised column
     for (int c = 0; c < RC; ++c) {
-      uint32_t w0 = 0, w1 = 0;
+      T w;
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc) {
         const int j = 4 * c + cc;
         const int h = j == 0 ? h0 : imax(0, h0 - oI - eI * j);
-        const uint32_t hv = j <= hw ? (uint32_t)imin(h, 255) : 0u;
-        if (cc < 2) w0 |= hv << (16 * cc); else w1 |= hv << (16 * (cc - 2));
+        rec_set(w, cc, j <= hw ? (uint32_t)imin(h, CK::MAXV) : 0u);
       }
-      my[c * 64] = make_uint2(w0, w1);
+      my[c * 64] = w;
     }
     // query codes, four per dword, column-major tile
     {
@@ -631,7 +711,7 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         // band (Sec. 5.1 (a)); the column leaving on the left is zeroed so
         // that everything left of beg stays zero
         if (beg < i - wb) {
-          *(unsigned short*)COL(beg) = 0;
+          COL(beg) = 0;
           beg = i - wb;
         }
         end = imin(imin(end, i + wb + 1), Lq);
@@ -640,7 +720,7 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         // value
         while (hw < end) {
           ++hw;
-          *(unsigned short*)COL(hw) = (unsigned short)imax(0, h0 - oI - eI * hw);
+          COL(hw) = (R)imax(0, h0 - oI - eI * hw);
         }
         const int tb = (tq >> (8 * (i & 3))) & 0xff;
         lo = pl[0];
@@ -667,33 +747,21 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         // next step, so LDS and L2 latency overlap a whole step of work
         int sa = ring_slot(c, RC);
         int sb = sa + 1 == RC ? 0 : sa + 1;
-        uint2 chA = my[sa * 64], chB = my[sb * 64];
+        T chA = my[sa * 64], chB = my[sb * 64];
         uint32_t qA = qt[c * 64], qB = qt[(c + 1) * 64];
         for (; c + 2 <= cf; c += 2) {
-          int sa2 = sb + 1 == RC ? 0 : sb + 1;
-          int sb2 = sa2 + 1 == RC ? 0 : sa2 + 1;
+          const int sa2 = sb + 1 == RC ? 0 : sb + 1;
+          const int sb2 = sa2 + 1 == RC ? 0 : sa2 + 1;
           {
             const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qA);
             qA = qt[(c + 2) * 64];
-            const int j0 = 4 * c;
-            uint32_t n0 = 0, n1 = 0;
-            BSW_CELL8(chA.x, 0, sc, 0, j0, n0, 0);
-            BSW_CELL8(chA.x, 16, sc, 1, j0 + 1, n0, 16);
-            BSW_CELL8(chA.y, 0, sc, 2, j0 + 2, n1, 0);
-            BSW_CELL8(chA.y, 16, sc, 3, j0 + 3, n1, 16);
-            my[sa * 64] = make_uint2(n0, n1);
+            my[sa * 64] = chunk_cells(chA, sc, 4 * c, hl, f, mkey, cp);
             chA = my[sa2 * 64];
           }
           {
             const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qB);
             qB = qt[(c + 3) * 64];
-            const int j0 = 4 * c + 4;
-            uint32_t n0 = 0, n1 = 0;
-            BSW_CELL8(chB.x, 0, sc, 0, j0, n0, 0);
-            BSW_CELL8(chB.x, 16, sc, 1, j0 + 1, n0, 16);
-            BSW_CELL8(chB.y, 0, sc, 2, j0 + 2, n1, 0);
-            BSW_CELL8(chB.y, 16, sc, 3, j0 + 3, n1, 16);
-            my[sb * 64] = make_uint2(n0, n1);
+            my[sb * 64] = chunk_cells(chB, sc, 4 * c + 4, hl, f, mkey, cp);
             chB = my[sb2 * 64];
           }
           sa = sa2;
@@ -701,13 +769,7 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         }
         if (c < cf) {
           const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qA);
-          const int j0 = 4 * c;
-          uint32_t n0 = 0, n1 = 0;
-          BSW_CELL8(chA.x, 0, sc, 0, j0, n0, 0);
-          BSW_CELL8(chA.x, 16, sc, 1, j0 + 1, n0, 16);
-          BSW_CELL8(chA.y, 0, sc, 2, j0 + 2, n1, 0);
-          BSW_CELL8(chA.y, 16, sc, 3, j0 + 3, n1, 16);
-          my[sa * 64] = make_uint2(n0, n1);
+          my[sa * 64] = chunk_cells(chA, sc, 4 * c, hl, f, mkey, cp);
           ++c;
         }
       }
@@ -715,17 +777,17 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         const int j0 = 4 * c;
         if (j0 < rend) {
           const int sl = ring_slot(c, RC);
-          uint2 ch = my[sl * 64];
+          T ch = my[sl * 64];
           const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qt[c * 64]);
 #pragma unroll
           for (int cc = 0; cc < 4; ++cc) {
             const int j = j0 + cc;
             if (j < rend) {
-              uint32_t& w = cc < 2 ? ch.x : ch.y;
-              const int sh = 16 * (cc & 1);
-              uint32_t nw = 0;
-              BSW_CELL8(w, sh, sc, cc, j, nw, 0);
-              w = (w & ~(0xffffu << sh)) | ((nw & 0xffffu) << sh);
+              const uint32_t r = rec_get(ch, cc);
+              constexpr uint32_t M = (1u << WB) - 1;
+              rec_set(ch, cc,
+                      cell<WB>(r & M, r >> WB, (int)(int8_t)(sc >> (8 * cc)), j, hl, f,
+                               mkey, cp));
             }
           }
           my[sl * 64] = ch;
@@ -733,7 +795,7 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
       }
       if (live) {
         // right edge (R8): H(i, end-1) at index end; E there is already 0
-        *(unsigned short*)COL(end) = (unsigned short)(hl & 0xff);
+        COL(end) = (R)(hl & CK::MAXV);
         // best score touching the end of the query (Sec. 5.4 (b))
         if (imax(beg, end) == Lq) {
           gi = hl >= gbest ? i : gi;
@@ -758,20 +820,20 @@ k_lane8(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         }
         if (live) {
           // shrink the band by its empty ends (Sec. 5.1 (c))
-          while (beg < end && *(const unsigned short*)COL(beg) == 0) ++beg;
+          while (beg < end && COL(beg) == 0) ++beg;
           int x = end;
-          while (x >= beg && *(const unsigned short*)COL(x) == 0) --x;
+          while (x >= beg && COL(x) == 0) --x;
           end = imin(x + 2, Lq);
         }
       }
     }
     unsigned long long my_cells = 0;
     if (valid) {
-      const int slack = P.amax - oeD > 0 ? P.amax - oeD : 0;
-      if (best + slack > 255) {
-        // some stored value may have needed more than 8 bits: rerun wide
+      const int slack = P.amax - P.oe_del > 0 ? P.amax - P.oe_del : 0;
+      if (best + slack > CK::MAXV) {
+        // some stored value may have needed a wider record: rerun wider
         const unsigned long long pos =
-            atomicAdd((unsigned long long*)&stw->ovf_range[1], 1ull);
+            atomicAdd((unsigned long long*)ovf_count, 1ull);
         ovf[pos] = pd;
       } else {
         my_cells = (unsigned long long)cells;
@@ -839,18 +901,24 @@ static int cls_cap(int cls) {
   return LW_CAP[cls - CLS_W32];
 }
 
-// LDS bytes per wave of a class
+// chunked classes (8-bit and 16-bit records) vs the legacy 32-bit kernel
+static bool chunked(int cls) { return cls < CLS_W32; }
+static int rec_bytes(int cls) { return cls < CLS_W16 ? 8 : 16; }
+
+// LDS bytes per wave of a class (chunked classes: without a ring)
 size_t lane_lds_per_wave(int cls) {
   const int cap = cls_cap(cls);
-  if (cls < CLS_W16) return (size_t)(cap / 4 + 1) * 64 * 8;
-  const size_t rec = cls < CLS_W32 ? 4 : 8;
-  return (size_t)(cap + 1) * 64 * rec + (size_t)cap * 64;
+  if (chunked(cls)) return (size_t)(cap / 4 + 1) * 64 * rec_bytes(cls);
+  return (size_t)(cap + 1) * 64 * 8 + (size_t)cap * 64;
 }
 
-// waves per workgroup: 8-bit classes run one wave per group; wide classes
-// as many as fit in 64 KiB of LDS (1..4)
+// LDS bytes per 64-lane chunk row of a chunked class
+size_t lane_chunk_row_bytes(int cls) { return (size_t)64 * rec_bytes(cls); }
+
+// waves per workgroup: chunked classes run one wave per group; the 32-bit
+// kernel as many as fit in 64 KiB of LDS (1..4)
 int lane_waves_per_block(int cls) {
-  if (cls < CLS_W16) return 1;
+  if (chunked(cls)) return 1;
   const size_t b = lane_lds_per_wave(cls);
   int w = (int)(65536 / b);
   return w < 1 ? 1 : (w > 4 ? 4 : w);
@@ -859,57 +927,61 @@ int lane_waves_per_block(int cls) {
 typedef void (*LaneFn)(const PairDesc*, const long long*, const uint8_t*,
                        const uint8_t*, const KParams*, bsw_result*, bsw_diag*,
                        uint32_t*, const Status*, unsigned long long*);
-typedef void (*Lane8Fn)(const PairDesc*, const long long*, const uint8_t*,
+typedef void (*LaneCFn)(const PairDesc*, const long long*, const uint8_t*,
                         const uint8_t*, const KParams*, bsw_result*, bsw_diag*,
-                        uint32_t*, const Status*, uint32_t*, PairDesc*, Status*, int,
+                        uint32_t*, const Status*, uint32_t*, PairDesc*, long long*, int,
                         int, unsigned long long*);
 
-static Lane8Fn lane8_fn(int cls, bool sym) {
-  static const Lane8Fn tab[2][NL8] = {
-      {k_lane8<32, false>, k_lane8<64, false>, k_lane8<96, false>, k_lane8<128, false>,
-       k_lane8<160, false>, k_lane8<192, false>, k_lane8<224, false>, k_lane8<256, false>},
-      {k_lane8<32, true>, k_lane8<64, true>, k_lane8<96, true>, k_lane8<128, true>,
-       k_lane8<160, true>, k_lane8<192, true>, k_lane8<224, true>, k_lane8<256, true>}};
-  return tab[sym ? 1 : 0][cls - CLS_L8];
+static LaneCFn lanec_fn(int cls, bool sym) {
+  static const LaneCFn tab8[2][NL8] = {
+      {k_lanec<32, false, 8>, k_lanec<64, false, 8>, k_lanec<96, false, 8>,
+       k_lanec<128, false, 8>, k_lanec<160, false, 8>, k_lanec<192, false, 8>,
+       k_lanec<224, false, 8>, k_lanec<256, false, 8>},
+      {k_lanec<32, true, 8>, k_lanec<64, true, 8>, k_lanec<96, true, 8>,
+       k_lanec<128, true, 8>, k_lanec<160, true, 8>, k_lanec<192, true, 8>,
+       k_lanec<224, true, 8>, k_lanec<256, true, 8>}};
+  static const LaneCFn tab16[2][NLW] = {
+      {k_lanec<32, false, 16>, k_lanec<64, false, 16>, k_lanec<128, false, 16>,
+       k_lanec<256, false, 16>},
+      {k_lanec<32, true, 16>, k_lanec<64, true, 16>, k_lanec<128, true, 16>,
+       k_lanec<256, true, 16>}};
+  return cls < CLS_W16 ? tab8[sym ? 1 : 0][cls - CLS_L8] : tab16[sym ? 1 : 0][cls - CLS_W16];
 }
 
 static LaneFn lanew_fn(int cls, bool persist) {
-  static const LaneFn tab[2][2 * NLW] = {
-      {k_lane<W16, 32, false>, k_lane<W16, 64, false>, k_lane<W16, 128, false>,
-       k_lane<W16, 256, false>, k_lane<W32, 32, false>, k_lane<W32, 64, false>,
-       k_lane<W32, 128, false>, k_lane<W32, 256, false>},
-      {k_lane<W16, 32, true>, k_lane<W16, 64, true>, k_lane<W16, 128, true>,
-       k_lane<W16, 256, true>, k_lane<W32, 32, true>, k_lane<W32, 64, true>,
-       k_lane<W32, 128, true>, k_lane<W32, 256, true>}};
-  return tab[persist ? 1 : 0][cls - CLS_W16];
+  static const LaneFn tab[2][NLW] = {
+      {k_lane<W32, 32, false>, k_lane<W32, 64, false>, k_lane<W32, 128, false>,
+       k_lane<W32, 256, false>},
+      {k_lane<W32, 32, true>, k_lane<W32, 64, true>, k_lane<W32, 128, true>,
+       k_lane<W32, 256, true>}};
+  return tab[persist ? 1 : 0][cls - CLS_W32];
 }
 
-// kernel symbol of a class (for 8-bit classes "persist" selects the
-// symmetric-gap variant; both take the same LDS)
-static const void* lane_sym(int cls, bool persist) {
-  return cls < CLS_W16 ? (const void*)lane8_fn(cls, persist)
-                       : (const void*)lanew_fn(cls, persist);
+// kernel symbol of a class (for chunked classes "flag" selects the
+// symmetric-gap variant, for the 32-bit kernel the persistent one)
+static const void* lane_sym(int cls, bool flag) {
+  return chunked(cls) ? (const void*)lanec_fn(cls, flag) : (const void*)lanew_fn(cls, flag);
 }
 
-hipError_t lane_setup(int cls, bool persist) {
+hipError_t lane_setup(int cls, bool flag) {
   const size_t lds = lane_lds_per_wave(cls) * lane_waves_per_block(cls);
-  return hipFuncSetAttribute(lane_sym(cls, persist),
+  return hipFuncSetAttribute(lane_sym(cls, flag),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 // resident workgroups per CU for a lane-mode class, given the LDS bytes
 // per workgroup (0 = the class's full row buffer)
-int lane_blocks_per_cu(int cls, bool persist, size_t lds) {
+int lane_blocks_per_cu(int cls, bool flag, size_t lds) {
   int nb = 0;
   const int wpb = lane_waves_per_block(cls);
   if (!lds) lds = lane_lds_per_wave(cls) * wpb;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_sym(cls, persist), wpb * 64,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_sym(cls, flag), wpb * 64,
                                                    lds) != hipSuccess)
     return 1;
   return nb < 1 ? 1 : nb;
 }
 
-// ring chunks of an 8-bit class for band half-widths up to wmax: enough
+// ring chunks of a chunked class for band half-widths up to wmax: enough
 // for the live band (4*RC > 2w' + 4, plus a spare chunk), and at least half
 // of the chunks a query of the class can touch, so that one conditional
 // subtraction maps every chunk index (at most full - 1) into the ring
@@ -920,7 +992,7 @@ int lane8_ring_chunks(int cls, int wmax) {
   return need >= full ? full : (int)need;
 }
 
-// HBM words of query tile per workgroup of an 8-bit class
+// HBM words of query tile per workgroup of a chunked class
 size_t lane8_qtile_words(int cls) { return ((size_t)cls_cap(cls) / 4 + 3) * 64; }
 
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s) {
@@ -964,13 +1036,14 @@ void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
                  const long long* range, const uint8_t* q, const uint8_t* t,
                  const KParams* kp, bsw_result* out, bsw_diag* diag,
                  uint32_t* tile_ctr, const Status* st, uint32_t* qtiles,
-                 PairDesc* ovf, Status* stw, int ring, bool sym,
+                 PairDesc* ovf, long long* ovf_count, int ring, bool sym,
                  unsigned long long* cls_cells, hipStream_t s) {
   const int wpb = lane_waves_per_block(cls);
-  if (cls < CLS_W16)
-    hipLaunchKernelGGL(lane8_fn(cls, sym), dim3(blocks), dim3(64), (size_t)ring * 512, s,
-                       desc, range, q, t, kp, out, diag, tile_ctr, st, qtiles, ovf, stw,
-                       persist ? 1 : 0, ring, cls_cells);
+  if (chunked(cls))
+    hipLaunchKernelGGL(lanec_fn(cls, sym), dim3(blocks), dim3(64),
+                       (size_t)ring * lane_chunk_row_bytes(cls), s, desc, range, q, t, kp,
+                       out, diag, tile_ctr, st, qtiles, ovf, ovf_count, persist ? 1 : 0,
+                       ring, cls_cells);
   else
     hipLaunchKernelGGL(lanew_fn(cls, persist), dim3(blocks), dim3(wpb * 64),
                        lane_lds_per_wave(cls) * wpb, s, desc, range, q, t, kp, out, diag,
