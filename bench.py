@@ -40,6 +40,107 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def traffic_from_profile(kernel, cells):
+    """HBM bytes per launch of a kernel from the committed counter profile
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain streaming kernel), if
+    the profile was taken on the current kernel source and the same work
+    (its cells per launch); else None."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1907_12931_amd", "csrc", "bsw_kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    prof_dir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(prof_dir):
+        return None
+    for name in sorted(os.listdir(prof_dir)):
+        if not name.endswith(".md"):
+            continue
+        text = open(os.path.join(prof_dir, name)).read()
+        fields = dict(re.findall(r"^- (\w+): `([^`]*)`", text, flags=re.M))
+        if (fields.get("kernel") == kernel and fields.get("source_sha256") == digest
+                and fields.get("cells_per_launch") == str(cells)
+                and "traffic_bytes_per_launch" in fields):
+            return int(fields["traffic_bytes_per_launch"])
+    return None
+
+
+def pinned(a):
+    """A copy of a host array in pinned (page-locked) memory, so that the
+    library's host-to-device copies run asynchronously at full rate."""
+    import numpy as np
+    import torch
+    a = np.ascontiguousarray(a)
+    buf = torch.empty(a.nbytes, dtype=torch.uint8, pin_memory=True)
+    out = buf.numpy().view(a.dtype).reshape(a.shape)
+    out[...] = a
+    return out
+
+
+def kernel_symbol(cls, scorings):
+    """The kernel template instance that runs a class (as profilers name it)."""
+    sym = "true" if all(x["o_del"] == x["o_ins"] and x["e_del"] == x["e_ins"]
+                        for x in scorings) else "false"
+    if cls == "long":
+        return "bsw::k_long"
+    if cls == "rerun16":
+        return f"bsw::k_lanec<256, {sym}, 16>"
+    if cls == "rerun32":
+        return "bsw::k_lane<2, 256, true>"
+    width, cap = cls[4:].split("_q")
+    if width == "32":
+        return f"bsw::k_lane<2, {cap}, true>"
+    return f"bsw::k_lanec<{cap}, {sym}, {width}>"
+
+
+def rho_key(r):
+    return f"load_{r:.1f}"
+
+
+def serve(bsw, synth, batch, host, capacity, rho, n_requests, seed=3):
+    """Open-loop serving run: request sizes log-uniform in [1e3, 1e5] pairs,
+    each a contiguous slice of the batch's host arrays (in pinned memory),
+    arriving as a Poisson process at rho x the batched path's capacity
+    (pairs/s).
+    Latency = submit -> results in the caller's buffers."""
+    import threading
+    import numpy as np
+    sizes = synth.serving_requests(n_requests=n_requests, seed=seed)
+    rng = np.random.default_rng(seed)
+    n = len(batch["h0"])
+    starts = rng.integers(0, n - sizes + 1)
+    gaps = rng.exponential(sizes / (rho * capacity))
+    arrivals = np.cumsum(gaps)
+    reqs = [{"q": host["q"], "t": host["t"],
+             "q_off": host["q_off"][a:a + m + 1], "t_off": host["t_off"][a:a + m + 1],
+             "h0": host["h0"][a:a + m], "scorings": batch["scorings"]}
+            for a, m in zip(starts.tolist(), sizes.tolist())]
+    tickets = [None] * n_requests
+    ready = threading.Semaphore(0)
+    with bsw.Server(batch["scorings"], max_inflight=2, hbm_budget=8 << 30) as srv:
+        def waiter():
+            for k in range(n_requests):
+                ready.acquire()
+                srv.wait(tickets[k])
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for k in range(n_requests):
+            delay = arrivals[k] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[k] = srv.submit(reqs[k])
+            ready.release()
+        th.join()
+        st = srv.stats()
+    return {"offered_pairs_per_s": round(rho * capacity), "requests": n_requests,
+            "pairs": st["pairs"], "batches": st["batches"],
+            "mean_batch_pairs": round(st["mean_batch_pairs"]),
+            "p50_ms": round(st["lat_p50_ms"], 3), "p99_ms": round(st["lat_p99_ms"], 3),
+            "p999_ms": round(st["lat_p999_ms"], 3), "max_ms": round(st["lat_max_ms"], 3),
+            "admit_wait_mean_ms": round(st["admit_wait_mean_ms"], 3),
+            "gcups": round(st["gcups"], 2), "window_s": round(st["window_s"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,8 +148,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--pairs", type=int, default=4_000_000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain streaming kernel over this many MiB "
+                         "(read once, written once): the calibration point for "
+                         "hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single "
@@ -60,6 +166,13 @@ def main():
     import torch
     from paper_1907_12931_amd import bsw, synth
 
+    if args.copy_mib:
+        x = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.bitwise_not(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
     workers = min(16, os.cpu_count() or 1)
     t0 = time.time()
     batch = synth.batched_mix(n=args.pairs, workers=workers)
@@ -69,8 +182,18 @@ def main():
     out, diag = bsw.alloc_outputs(n, with_diag=True)
     torch.cuda.synchronize()
 
-    def run_path(path, steps, warmup):
-        ctx = bsw.Context(path=path)
+    import tempfile
+    tune_cache = os.path.join(tempfile.mkdtemp(prefix="bsw_tune_"), "tune.json")
+    tuned = {}
+
+    def run_path(path, steps, warmup, graph=True):
+        ctx = bsw.Context(path=path, graph=graph,
+                          tune_cache=tune_cache if path == bsw.PATH_BATCHED else None)
+        if path == bsw.PATH_BATCHED and not tuned:
+            # launch shapes from the autotuner, on this batch (untimed)
+            ms, shape = ctx.tune(dev, batch["scorings"], out, reps=2)
+            tuned.update(shape, tune_best_ms=round(ms, 3))
+            log(f"tuned: {tuned}")
         ctx.extend_device(dev, batch["scorings"], out, diag)  # cells + warm
         cells = int(diag.view(torch.int64).view(n, 2)[:, 1].sum().item())
         for _ in range(warmup):
@@ -97,31 +220,50 @@ def main():
                 "dp_ms": float(np.mean(dp_ms)), "prep_ms": float(np.mean(prep_ms)),
                 "dp_launches": launches, "kernels": kernels}
 
+    # headline: the batched path as a graph replay (its kernels overlap on
+    # side streams, and a graph's inner steps carry no event timestamps)
     b = run_path(bsw.PATH_BATCHED, args.steps, args.warmup)
     cells = b["cells"]
     gcups = cells / (b["ms_per_step"] / 1e3) / 1e9
-    log(f"batched: {b}")
-    plain = None
-    if not args.no_plain:
-        p = run_path(bsw.PATH_PLAIN, args.steps, args.warmup)
-        log(f"plain: {p}")
-        plain = {"value": round(p["cells"] / (p["ms_per_step"] / 1e3) / 1e9, 2),
-                 "unit": "GCUPS", "ms_per_step": round(p["ms_per_step"], 3),
-                 "dp_ms": round(p["dp_ms"], 3), "dp_launches": p["dp_launches"]}
+    log(f"batched (graph): {b}")
+    # the plain path runs one kernel at a time on one stream: its per-launch
+    # HIP events time each DP kernel alone
+    p = run_path(bsw.PATH_PLAIN, args.steps, args.warmup)
+    assert p["cells"] == cells
+    log(f"plain: {p}")
+    plain = {"value": round(p["cells"] / (p["ms_per_step"] / 1e3) / 1e9, 2),
+             "unit": "GCUPS", "ms_per_step": round(p["ms_per_step"], 3),
+             "dp_ms": round(p["dp_ms"], 3), "dp_launches": p["dp_launches"]}
+
+    serving = None
+    if not args.no_serve:
+        capacity = n / (b["ms_per_step"] / 1e3)  # pairs/s of the batched path
+        # request data in pinned host memory, as a serving front end keeps it
+        host = {k: pinned(batch[k]) for k in ("q", "t", "q_off", "t_off", "h0")}
+        serving = {rho_key(r): serve(bsw, synth, batch, host, capacity, r,
+                                     args.serve_requests)
+                   for r in (0.5, 0.8)}
+        log(f"serving: {serving}")
 
     # dominant kernel: the DP launch with the largest device time; its
     # algorithmic work is its settled cells x OPS_PER_CELL int32 operations
-    dom, dk = max(b["kernels"].items(), key=lambda kv: kv[1]["ms"])
+    dom, dk = max(p["kernels"].items(), key=lambda kv: kv[1]["ms"])
     achieved = dk["cells"] * OPS_PER_CELL / (dk["ms"] / 1e3) / 1e12
-    all_dp = cells * OPS_PER_CELL / (b["dp_ms"] / 1e3) / 1e12
+    step = cells * OPS_PER_CELL / (b["ms_per_step"] / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3),
                 "peak": round(PEAK_INT_TOPS, 3), "unit": "TOP/s",
                 "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": None,
-                "kernel": f"k_lane8 class {dom}", "kernel_ms": round(dk["ms"], 3),
+                "kernel": f"{kernel_symbol(dom, batch['scorings'])} (class {dom})",
+                "kernel_ms": round(dk["ms"], 3),
                 "kernel_cells": dk["cells"], "ops_per_cell": OPS_PER_CELL,
-                "all_dp_achieved": round(all_dp, 3),
-                "all_dp_frac": round(all_dp / PEAK_INT_TOPS, 4),
-                "per_kernel_ms": {k: round(v["ms"], 3) for k, v in b["kernels"].items()}}
+                "timed_on": "plain path (each DP kernel alone on one stream)",
+                "batched_step_achieved": round(step, 3),
+                "batched_step_frac": round(step / PEAK_INT_TOPS, 4),
+                "per_kernel_ms": {k: round(v["ms"], 3) for k, v in p["kernels"].items()
+                                  if v["cells"]},
+                "per_kernel_gcups": {k: round(v["cells"] / v["ms"] / 1e6, 1)
+                                     for k, v in p["kernels"].items() if v["cells"]}}
+    roofline["traffic"] = traffic_from_profile(roofline["kernel"], dk["cells"])
 
     cpu = None
     if not args.no_cpu:
@@ -156,8 +298,9 @@ def main():
                                "100/150/250 bp sources, tlen <= qlen+200, 20% z-drop, "
                                "match 1 mismatch -4 gap 6+k w 100 zdrop 100 bonus 5",
                    "pairs": n, "cells": cells, "path": "batched",
-                   "dp_launches": b["dp_launches"], "prep_bin_ms": round(b["prep_ms"], 3)},
-        "plain": plain, "roofline": roofline, "cpu_baseline": cpu,
+                   "dp_launches": b["dp_launches"], "graph": True, "tuned": tuned,
+                   "prep_bin_ms": round(p["prep_ms"], 3)},
+        "plain": plain, "serving": serving, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
 

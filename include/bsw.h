@@ -103,10 +103,19 @@ typedef struct bsw_ctx_opts {
   int32_t device;          /* HIP device ordinal                           */
   int32_t min_lane_bits;   /* 0 = pick 8/16/32 from each pair's score bound;
                             * 16 or 32 forces at least that width           */
-  int32_t force_mode;      /* 0 = by length, 1 = lane mode, 2 = wave mode   */
+  int32_t reserved;        /* must be 0                                     */
   int32_t path;            /* BSW_PATH_BATCHED or BSW_PATH_PLAIN            */
-  size_t  hbm_budget;      /* arena cap in bytes; 0 = 8 GiB                 */
-  const char* tune_cache;  /* autotuner JSON cache path, or NULL            */
+  size_t  hbm_budget;      /* cap on the context's device arena in bytes
+                            * (0 = none); a call that would need more fails
+                            * with BSW_ETOOBIG before any work is enqueued   */
+  const char* tune_cache;  /* JSON file of tuned launch shapes, or NULL: an
+                            * entry for the device, band limit, gap symmetry
+                            * and min_lane_bits of a call is used when
+                            * present; bsw_ctx_tune adds or replaces it      */
+  int32_t no_graph;        /* batched path: 0 = capture the pipeline into a
+                            * HIP graph on the first call with a given set of
+                            * pointers and shapes and replay it on later
+                            * calls; 1 = enqueue every step eagerly          */
 } bsw_ctx_opts;
 
 /* Create a context on a device.  Returns BSW_EDEVICE when the device is
@@ -142,6 +151,25 @@ int bsw_extend_batch_device(bsw_ctx* ctx, int64_t n,
                             bsw_result* out, bsw_diag* diag,
                             void* stream, int32_t async);
 
+/* Autotuner of the batched path.  Runs the batched path eagerly over a
+ * device batch (arguments as bsw_extend_batch_device; results are written
+ * to out as by a normal call) once per candidate launch shape: side streams
+ * the kernel classes are spread over (4, 2, 1), share of resident groups
+ * per CU for the 8-bit classes (100%, 50%), and whether pairs whose score
+ * bound needs 16 bits are tried at 8 bits first (yes, no).  Each candidate
+ * gets one warm-up call and reps (1..100) timed calls; the fastest device
+ * time wins.  The winner is used by every later batched call of the context
+ * with the same band limit and gap symmetry, and is stored in tune_cache
+ * when one is set.  *best_ms (nullable) receives its time.  Blocking. */
+int bsw_ctx_tune(bsw_ctx* ctx, int64_t n, const uint8_t* q, const uint64_t* q_off,
+                 const uint8_t* t, const uint64_t* t_off, const int32_t* h0,
+                 const uint8_t* param_id, const bsw_params* params, int32_t n_params,
+                 bsw_result* out, int32_t reps, double* best_ms);
+
+/* The context's current launch shape: out3 = {side streams, 8-bit share of
+ * resident groups in percent, 16-bit pairs tried at 8 bits (0/1)}. */
+int bsw_ctx_tune_info(bsw_ctx* ctx, int32_t out3[3]);
+
 /* Wait for the last asynchronous call on ctx and return its status
  * (BSW_EINVAL with the first bad pair in bsw_last_error if a pair was
  * rejected on the device). */
@@ -149,20 +177,99 @@ int bsw_ctx_wait(bsw_ctx* ctx);
 
 /* Timing of the last completed call's device work, in milliseconds:
  * [0] = whole pipeline (first to last kernel), [1] = prepare and bin,
- * [2] = DP kernels, [3] = number of DP kernel launches.  Returns BSW_OK. */
+ * [2] = DP kernels, [3] = number of DP kernel launches.  A call that ran as
+ * a graph replay has [0] only ([1] = [2] = 0).  Returns BSW_OK. */
 int bsw_ctx_last_timing(bsw_ctx* ctx, double out4[4]);
 
 /* Per-launch record of the last completed call's DP kernels: for launch k,
  * cls[k] = kernel class (see bsw_class_name), cells[k] = band cells the
  * launch settled, ms[k] = its device time from HIP events on the launch
- * stream.  Any output pointer may be NULL; at most max entries are
- * written.  Returns the number of launches (may exceed max). */
+ * stream (0 for a call that ran as a graph replay: events inside a graph
+ * carry no timestamps; use a context with no_graph = 1 to time launches).
+ * Any output pointer may be NULL; at most max entries are written.
+ * Returns the number of launches (may exceed max). */
 int bsw_ctx_last_kernels(bsw_ctx* ctx, int32_t* cls, int64_t* cells, double* ms,
                          int32_t max);
 
 /* Name of a kernel class ("lane8_q256" = one pair per lane, 8-bit row
  * buffer, queries up to 256; "rerun16" = 16-bit rerun of 8-bit overflows). */
 const char* bsw_class_name(int32_t cls);
+
+/* ------------------------------------------------------------------------
+ * Serving (the paper's reorganisation of the work into large batches with
+ * buffers reused across them, Sec. 3.2 and 5.3.1, applied to requests that
+ * arrive over time).  A server owns one device arena of hbm_budget bytes
+ * that holds the data of every admitted request (sequences, offsets, h0,
+ * param_id and a status block) from admission until completion, and
+ * max_inflight execution slots (each a context with its own streams and
+ * workspace).  Requests are admitted strictly in arrival order while the
+ * head request fits in the free arena space; admission copies the request
+ * to the device and checks its codes there.  Whenever a slot is free, every
+ * admitted request whose data is resident and valid joins one batch (up to
+ * max_batch_pairs pairs), which runs the batched path; results are copied
+ * back into each request's own output buffer.  A request's results equal
+ * those of the same pairs run alone (pairs are independent).
+ * ---------------------------------------------------------------------- */
+typedef struct bsw_server bsw_server;
+
+typedef struct bsw_server_opts {
+  int32_t device;
+  int32_t max_inflight;     /* slots (concurrent batches), 1..8; 0 = 2      */
+  int64_t max_batch_pairs;  /* pairs per batch cap; 0 = 4,194,304; a larger
+                             * request runs as a batch of its own            */
+  size_t  hbm_budget;       /* arena for resident request data; 0 = 8 GiB   */
+  int32_t max_queued;       /* submitted, not yet admitted requests before
+                             * bsw_server_submit returns BSW_EBUSY; 0 = 65536 */
+  int32_t min_lane_bits;    /* as in bsw_ctx_opts                          */
+} bsw_server_opts;
+
+/* Latency and throughput since creation or the last reset.  Latency runs
+ * from bsw_server_submit to the results being in the caller's buffers. */
+typedef struct bsw_server_report {
+  int64_t submitted;        /* accepted by bsw_server_submit               */
+  int64_t completed;        /* finished with BSW_OK                        */
+  int64_t failed;           /* finished with an error (invalid pair)       */
+  int64_t batches;          /* batches run                                 */
+  int64_t pairs;            /* pairs of the completed requests             */
+  int64_t cells;            /* band cells settled by the batches           */
+  double  mean_batch_pairs;
+  double  lat_p50_ms, lat_p99_ms, lat_p999_ms, lat_max_ms;
+  double  admit_wait_mean_ms, admit_wait_p99_ms; /* submit -> admission    */
+  double  window_s;         /* first submit -> last completion             */
+  double  gcups;            /* cells / window_s / 1e9                      */
+} bsw_server_report;
+
+/* Create a server on a device with one scoring table for all requests
+ * (n_params <= 256, validated as for bsw_extend_batch).  The arena and the
+ * slots are allocated here; BSW_ENOMEM if they do not fit. */
+int bsw_server_create(bsw_server** out, const bsw_server_opts* opts,
+                      const bsw_params* params, int32_t n_params);
+/* Finish every submitted request, then release the server. */
+void bsw_server_destroy(bsw_server* srv);
+
+/* Submit a request of n >= 1 pairs in host memory (same layout and rules
+ * as bsw_extend_batch; param_id indexes the server's table).  Offsets,
+ * lengths, h0 and param_id are checked here (BSW_EINVAL); the codes are
+ * checked on the device at admission, and a bad code fails the request at
+ * bsw_server_wait.  Returns BSW_ETOOBIG if the request needs more than the
+ * whole arena, BSW_EBUSY if max_queued requests are waiting for admission.
+ * On success *ticket identifies the request.  Every buffer of the request,
+ * out and diag (nullable) included, must stay valid and unchanged until
+ * bsw_server_wait has returned for the ticket. */
+int bsw_server_submit(bsw_server* srv, int64_t n,
+                      const uint8_t* q, const uint64_t* q_off,
+                      const uint8_t* t, const uint64_t* t_off,
+                      const int32_t* h0, const uint8_t* param_id,
+                      bsw_result* out, bsw_diag* diag, uint64_t* ticket);
+
+/* Wait up to timeout_ms (< 0 = no limit) for a request; returns its status
+ * (BSW_OK, or BSW_EINVAL for a request with a bad code) and forgets the
+ * ticket, or BSW_ETIMEOUT (the ticket stays valid), or BSW_EINVAL for an
+ * unknown ticket.  Any thread may wait; each ticket is waited for once. */
+int bsw_server_wait(bsw_server* srv, uint64_t ticket, int32_t timeout_ms);
+
+/* Fill *out; reset != 0 starts a new measurement window. */
+int bsw_server_stats(bsw_server* srv, bsw_server_report* out, int32_t reset);
 
 /* Text of the calling thread's most recent error ("" if none). */
 const char* bsw_last_error(void);

@@ -39,8 +39,24 @@ class Params(ctypes.Structure):
 
 class CtxOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("min_lane_bits", ctypes.c_int32),
-                ("force_mode", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_size_t), ("tune_cache", ctypes.c_char_p)]
+                ("reserved", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t), ("tune_cache", ctypes.c_char_p),
+                ("no_graph", ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_batch_pairs", ctypes.c_int64), ("hbm_budget", ctypes.c_size_t),
+                ("max_queued", ctypes.c_int32), ("min_lane_bits", ctypes.c_int32)]
+
+
+class ServerReport(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("submitted", "completed", "failed", "batches", "pairs", "cells")] + \
+               [(k, ctypes.c_double) for k in
+                ("mean_batch_pairs", "lat_p50_ms", "lat_p99_ms", "lat_p999_ms",
+                 "lat_max_ms", "admit_wait_mean_ms", "admit_wait_p99_ms", "window_s",
+                 "gcups")]
 
 
 RESULT_DTYPE = np.dtype([("score", "<i4"), ("qle", "<i4"), ("tle", "<i4"),
@@ -91,6 +107,24 @@ def lib():
         L.bsw_class_name.argtypes = [ctypes.c_int32]
         L.bsw_ctx_last_timing.restype = ctypes.c_int
         L.bsw_ctx_last_timing.argtypes = [_VP, ctypes.POINTER(ctypes.c_double)]
+        L.bsw_ctx_tune.restype = ctypes.c_int
+        L.bsw_ctx_tune.argtypes = [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP,
+                                   ctypes.POINTER(Params), ctypes.c_int32, _VP,
+                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.bsw_ctx_tune_info.restype = ctypes.c_int
+        L.bsw_ctx_tune_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
+        L.bsw_server_create.restype = ctypes.c_int
+        L.bsw_server_create.argtypes = [ctypes.POINTER(_VP), ctypes.POINTER(ServerOpts),
+                                        ctypes.POINTER(Params), ctypes.c_int32]
+        L.bsw_server_destroy.restype = None
+        L.bsw_server_destroy.argtypes = [_VP]
+        L.bsw_server_submit.restype = ctypes.c_int
+        L.bsw_server_submit.argtypes = [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP,
+                                        _VP, _VP, ctypes.POINTER(ctypes.c_uint64)]
+        L.bsw_server_wait.restype = ctypes.c_int
+        L.bsw_server_wait.argtypes = [_VP, ctypes.c_uint64, ctypes.c_int32]
+        L.bsw_server_stats.restype = ctypes.c_int
+        L.bsw_server_stats.argtypes = [_VP, ctypes.POINTER(ServerReport), ctypes.c_int32]
         if L.bsw_abi_version() != 1:
             raise BswError(EDEVICE, "libbsw.so ABI version mismatch")
         _lib = L
@@ -124,10 +158,10 @@ def _ptr(a):
 class Context:
     """A library context on one device (see ``bsw_ctx_create``)."""
 
-    def __init__(self, device=0, min_lane_bits=0, force_mode=0, path=PATH_BATCHED,
-                 hbm_budget=0, tune_cache=None):
-        o = CtxOpts(device, min_lane_bits, force_mode, path, hbm_budget,
-                    tune_cache.encode() if tune_cache else None)
+    def __init__(self, device=0, min_lane_bits=0, path=PATH_BATCHED,
+                 hbm_budget=0, tune_cache=None, graph=True):
+        o = CtxOpts(device, min_lane_bits, 0, path, hbm_budget,
+                    tune_cache.encode() if tune_cache else None, 0 if graph else 1)
         h = _VP()
         _check(lib().bsw_ctx_create(ctypes.byref(h), ctypes.byref(o)))
         self._h = h
@@ -185,6 +219,25 @@ class Context:
     def wait(self):
         _check(lib().bsw_ctx_wait(self._h))
 
+    def tune(self, dev, scorings, out, reps=2):
+        """Autotune the batched path's launch shapes on a device batch;
+        returns (best_ms, shape dict)."""
+        n = dev["h0"].numel()
+        params = make_params(scorings)
+        pid = dev.get("param_id")
+        ms = ctypes.c_double(0)
+        _check(lib().bsw_ctx_tune(
+            self._h, n, dev["q"].data_ptr(), dev["q_off"].data_ptr(),
+            dev["t"].data_ptr(), dev["t_off"].data_ptr(), dev["h0"].data_ptr(),
+            pid.data_ptr() if pid is not None else None, params, len(params),
+            out.data_ptr(), reps, ctypes.byref(ms)))
+        return ms.value, self.tune_info()
+
+    def tune_info(self):
+        v = (ctypes.c_int32 * 3)()
+        _check(lib().bsw_ctx_tune_info(self._h, v))
+        return {"side_streams": v[0], "occ8_pct": v[1], "spec16": v[2]}
+
     def last_kernels(self):
         """Per DP launch of the last call: list of (class name, cells, ms)."""
         cls = np.zeros(32, dtype=np.int32)
@@ -230,3 +283,76 @@ def outputs_to_numpy(out, diag=None):
     if diag is None:
         return r
     return r, diag.cpu().numpy().view(DIAG_DTYPE)
+
+
+class Server:
+    """Serving loop of the library (bsw_server_*): requests are submitted
+    from host memory, admitted in arrival order under the device budget and
+    run in batches formed from every resident request when a slot frees."""
+
+    def __init__(self, scorings, device=0, max_inflight=2, max_batch_pairs=0,
+                 hbm_budget=0, max_queued=0, min_lane_bits=0):
+        o = ServerOpts(device, max_inflight, max_batch_pairs, hbm_budget, max_queued,
+                       min_lane_bits)
+        params = make_params(scorings)
+        h = _VP()
+        _check(lib().bsw_server_create(ctypes.byref(h), ctypes.byref(o), params,
+                                       len(params)))
+        self._h = h
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bsw_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, batch, with_diag=False):
+        """Submit a host batch (see ``synth``); returns a ticket."""
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            return a if a.size else np.zeros(1, dtype=dt)
+        q = arr(batch["q"], np.uint8)
+        t = arr(batch["t"], np.uint8)
+        qo = np.ascontiguousarray(batch["q_off"], dtype=np.uint64)
+        to = np.ascontiguousarray(batch["t_off"], dtype=np.uint64)
+        h0 = np.ascontiguousarray(batch["h0"], dtype=np.int32)
+        pid = batch.get("param_id")
+        pid = None if pid is None else np.ascontiguousarray(pid, dtype=np.uint8)
+        n = len(h0)
+        out = np.zeros(n, dtype=RESULT_DTYPE)
+        diag = np.zeros(n, dtype=DIAG_DTYPE) if with_diag else None
+        tk = ctypes.c_uint64(0)
+        _check(lib().bsw_server_submit(
+            self._h, n, q.ctypes.data, qo.ctypes.data, t.ctypes.data, to.ctypes.data,
+            h0.ctypes.data, _ptr(pid), out.ctypes.data, _ptr(diag), ctypes.byref(tk)))
+        # the library reads these buffers until the request completes
+        self._live[tk.value] = (q, t, qo, to, h0, pid, out, diag)
+        return tk.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        """Results (and diagnostics if asked at submit) of a ticket."""
+        rc = lib().bsw_server_wait(self._h, ticket, timeout_ms)
+        if rc == ETIMEOUT:
+            raise BswError(rc, last_error())
+        keep = self._live.pop(ticket, None)
+        _check(rc)
+        out, diag = keep[6], keep[7]
+        return (out, diag) if diag is not None else out
+
+    def stats(self, reset=False):
+        r = ServerReport()
+        _check(lib().bsw_server_stats(self._h, ctypes.byref(r), 1 if reset else 0))
+        return {k: getattr(r, k) for k, _ in ServerReport._fields_}

@@ -13,11 +13,13 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
 #include "../../include/bsw.h"
 #include "bsw_internal.h"
+#include "bsw_runtime.h"
 
 namespace bsw {
 size_t lane_lds_per_wave(int cls);
@@ -27,19 +29,18 @@ int lane_blocks_per_cu(int cls, bool persist, size_t lds);
 int lane8_ring_chunks(int cls, int wmax);
 size_t lane8_qtile_words(int cls);
 size_t lane_chunk_row_bytes(int cls);
-void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
 void launch_prep(int64_t n, const uint8_t* q, const uint8_t* t, const uint64_t* q_off,
-                 const uint64_t* t_off, const int32_t* h0, const uint8_t* pid,
-                 int n_params, const KParams* kp, int min_bits, int force_mode,
-                 uint32_t* keys, uint32_t* hist, Status* st, hipStream_t s);
-void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
-                  hipStream_t s);
+                 const uint64_t* q_end, const uint64_t* t_off, const uint64_t* t_end,
+                 const int32_t* h0, const uint8_t* pid, int n_params, const KParams* kp,
+                 int min_bits, int spec16, uint32_t* keys, uint32_t* hist, Status* st,
+                 hipStream_t s);
 void launch_scan(const uint32_t* hist, uint32_t* cursor, long long* cls_range,
                  hipStream_t s);
-void launch_scatter(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
-                    const int32_t* h0, const uint8_t* pid, const uint32_t* keys,
-                    uint32_t* cursor, PairDesc* desc, const Status* st,
-                    hipStream_t s);
+void launch_scatter(int64_t n, const uint64_t* q_off, const uint64_t* q_end,
+                    const uint64_t* t_off, const uint64_t* t_end, const int32_t* h0,
+                    const uint8_t* pid, const uint32_t* keys, uint32_t* cursor,
+                    PairDesc* desc, const Status* st, hipStream_t s);
+
 void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
                  const long long* range, const uint8_t* q, const uint8_t* t,
                  const KParams* kp, bsw_result* out, bsw_diag* diag,
@@ -76,25 +77,36 @@ int fail(int code, const char* fmt, ...) {
                   "%s failed: %s", #expr, hipGetErrorString(e_));             \
   } while (0)
 
-// A growable device buffer.
+// Device bytes a context may hold (0 = no cap) and holds.
+struct Budget {
+  size_t limit = 0;
+  size_t used = 0;
+};
+
+// A growable device buffer, counted against its context's budget.
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  Budget* b = nullptr;
   int ensure(size_t bytes) {
     if (bytes <= cap) return BSW_OK;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
-    size_t want = std::max(bytes, (size_t)1 << 20);
+    const size_t want = std::max(bytes, (size_t)1 << 20);
+    if (b && b->limit && b->used - cap + want > b->limit)
+      return fail(BSW_ETOOBIG, "the call needs %zu more device bytes than the context's "
+                  "budget of %zu", b->used - cap + want - b->limit, b->limit);
+    release();
     if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
       p = nullptr;
       return fail(BSW_ENOMEM, "device allocation of %zu bytes failed", want);
     }
     cap = want;
+    if (b) b->used += cap;
     return BSW_OK;
   }
   void release() {
     if (p) (void)hipFree(p);
+    if (b) b->used -= cap;
     p = nullptr;
     cap = 0;
   }
@@ -179,6 +191,38 @@ KParams to_kparams(const bsw_params& p) {
   return k;
 }
 
+
+// Launch shapes of the batched path that the tuner chooses.
+struct Tune {
+  int nside = 4;    // side streams the classes are spread over (1, 2 or 4)
+  int occ8 = 100;   // percent of the resident groups per CU for 8-bit classes
+  int spec16 = 1;   // try pairs whose bound needs 16 bits at 8 bits first
+  bool operator==(const Tune& o) const {
+    return nside == o.nside && occ8 == o.occ8 && spec16 == o.spec16;
+  }
+};
+
+// What a captured batched pipeline depends on besides the scoring values.
+struct GraphKey {
+  Args a;
+  hipStream_t s;
+  void* ws;
+  void* qt;
+  void* lb;
+  int wmax;
+  bool sym;
+  Tune tune;
+};
+
+bool same_key(const GraphKey& x, const GraphKey& y) {
+  const Args &a = x.a, &b = y.a;
+  return a.n == b.n && a.q == b.q && a.q_off == b.q_off && a.t == b.t && a.t_off == b.t_off &&
+         a.h0 == b.h0 && a.pid == b.pid && a.n_params == b.n_params && a.out == b.out &&
+         a.diag == b.diag && a.q_end == b.q_end && a.t_end == b.t_end &&
+         a.codes_checked == b.codes_checked && x.s == y.s && x.ws == y.ws && x.qt == y.qt &&
+         x.lb == y.lb && x.wmax == y.wmax && x.sym == y.sym && x.tune == y.tune;
+}
+
 }  // namespace
 
 struct bsw_ctx {
@@ -202,6 +246,7 @@ struct bsw_ctx {
   int n_launch = 0;
   double lms[MAXL] = {};
   unsigned long long lcells[MAXL] = {};
+  Budget budget;
   DevBuf ws;       // workspace
   DevBuf in;       // staged host inputs
   DevBuf res;      // staged results (host API)
@@ -214,11 +259,20 @@ struct bsw_ctx {
   int blocks_per_cu[2][NCLS] = {};
   // occupancy of the chunked classes by (symmetric variant, ring chunks)
   int occc[2][NCLS][80] = {};
-  int last_status = BSW_OK;
   bool pending = false;
   hipStream_t pending_stream = nullptr;
+  bool graph_call = false;  // the last call ran as a graph replay
+  Status* last_st = nullptr;  // device status block of the last call
   double timing[4] = {0, 0, 0, 0};
-  int n_dp_launches = 0;
+  // captured batched pipeline and what it was captured for
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey;
+  int n_graph_launch = 0;
+  // launch shapes of the batched path (defaults, a cache entry or
+  // bsw_ctx_tune's choice)
+  Tune tune;
+  char dev_name[64] = {0};
+  std::string tune_key;  // cache entry the current shapes came from
 };
 
 namespace {
@@ -228,62 +282,352 @@ int set_device(bsw_ctx* c) {
   return BSW_OK;
 }
 
-// Enqueue prepare + bin, wait for the class counts, then enqueue the DP
-// kernels.  All pointers are device pointers.
-int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
-                 const uint8_t* t, const uint64_t* t_off, const int32_t* h0,
-                 const uint8_t* pid, int32_t n_params, bsw_result* out,
-                 bsw_diag* diag, hipStream_t s) {
-  int wmax = 0;
-  bool sym = true;
+
+// Workspace pointers of a call with n pairs.
+struct Work {
+  uint32_t* hist;
+  Status* st;
+  uint32_t* ctr;
+  uint32_t* cursor;
+  long long* cls_range;
+  PairDesc* ovf;
+  PairDesc* ovf2;
+  uint32_t* keys;
+  PairDesc* desc;
+  uint32_t* zero;
+  int64_t zero_words;
+};
+
+Work carve(char* base, const Layout& L) {
+  Work w;
+  w.hist = (uint32_t*)(base + L.hist);
+  w.st = (Status*)(base + L.status);
+  w.ctr = (uint32_t*)(base + L.ctr);
+  w.cursor = (uint32_t*)(base + L.cursor);
+  w.cls_range = (long long*)(base + L.cls_range);
+  w.ovf = (PairDesc*)(base + L.ovf);
+  w.ovf2 = (PairDesc*)(base + L.ovf2);
+  w.keys = (uint32_t*)(base + L.keys);
+  w.desc = (PairDesc*)(base + L.desc);
+  w.zero = (uint32_t*)(base + L.zero_beg);
+  w.zero_words = (int64_t)((L.zero_end - L.zero_beg) / 4);
+  return w;
+}
+
+// Scoring facts the launch shapes depend on.
+void scan_params(const bsw_ctx* c, int n_params, int* wmax, bool* sym) {
+  *wmax = 0;
+  *sym = true;
   for (int i = 0; i < n_params; ++i) {
-    wmax = std::max(wmax, c->h_kp[i].w);
-    sym = sym && c->h_kp[i].o_del == c->h_kp[i].o_ins && c->h_kp[i].e_del == c->h_kp[i].e_ins;
+    *wmax = std::max(*wmax, c->h_kp[i].w);
+    *sym = *sym && c->h_kp[i].o_del == c->h_kp[i].o_ins &&
+           c->h_kp[i].e_del == c->h_kp[i].e_ins;
   }
-  const Layout L = layout_for(n);
+}
+
+// Resident groups per CU of a chunked class with a ring of rg chunks
+// (cached per context).
+int chunked_per_cu(bsw_ctx* c, int cls, bool sym, int rg) {
+  int& occ = c->occc[sym ? 1 : 0][cls][rg];
+  if (!occ) occ = lane_blocks_per_cu(cls, sym, (size_t)rg * lane_chunk_row_bytes(cls));
+  return occ;
+}
+
+// validation, histogram, scan and scatter into class lists
+void enqueue_prep_bin(bsw_ctx* c, const Args& a, const Work& w, hipStream_t s) {
+  launch_fill(w.zero, w.zero_words, s);
+  const uint64_t* qe = a.q_end ? a.q_end : a.q_off + 1;
+  const uint64_t* te = a.t_end ? a.t_end : a.t_off + 1;
+  launch_prep(a.n, a.q, a.t, a.q_off, qe, a.t_off, te, a.h0, a.pid, a.n_params, c->d_kp,
+              c->opts.min_lane_bits, c->tune.spec16, w.keys, w.hist, w.st, s);
+  if (!a.codes_checked) {
+    launch_codes(a.q, a.q_off, a.n, w.st, s);
+    launch_codes(a.t, a.t_off, a.n, w.st, s);
+  }
+  launch_scan(w.hist, w.cursor, w.cls_range, s);
+  launch_scatter(a.n, a.q_off, qe, a.t_off, te, a.h0, a.pid, w.keys, w.cursor, w.desc, w.st,
+                 s);
+}
+
+// launch bracketing: start/end events on the launch's stream (not inside
+// a graph capture, where events carry no timestamps)
+int begin_launch(bsw_ctx* c, int cls, hipStream_t ls) {
+  c->lcls[c->n_launch] = cls;
+  if (!c->graph_call) HIPCHK(hipEventRecord(c->lev0[c->n_launch], ls));
+  return BSW_OK;
+}
+int end_launch(bsw_ctx* c, hipStream_t ls) {
+  if (!c->graph_call) HIPCHK(hipEventRecord(c->lev[c->n_launch], ls));
+  ++c->n_launch;
+  return BSW_OK;
+}
+
+// persistent groups per CU of a class: what fits, scaled for the 8-bit
+// classes by the tuned share
+int tuned_per_cu(const bsw_ctx* c, int cls, int fit) {
+  if (cls >= CLS_W16) return fit;
+  const int t = fit * c->tune.occ8 / 100;
+  return t < 1 ? 1 : t;
+}
+
+constexpr int R1CLS = CLS_W16 + NLW - 1;  // chunked 16-bit rerun of 8-bit overflows
+constexpr int R2CLS = CLS_W32 + NLW - 1;  // 32-bit rerun of 16-bit overflows
+
+// Launch shapes of the batched path.  They depend only on the band limit,
+// the gap symmetry and the device, never on the data: every class gets a
+// full persistent grid that drains its list from a device-side counter and
+// exits at once when the list is empty.
+struct BatchedPlan {
+  int64_t blocks[NCLS + 2] = {};  // per class, then the two reruns
+  int ring[NCLS + 2] = {};
+  size_t qt_off[NCLS + 2] = {};
+  size_t qt_words = 0;
+};
+
+BatchedPlan plan_batched(bsw_ctx* c, int wmax, bool sym) {
+  BatchedPlan p;
+  for (int cls = 0; cls < CLS_LONG; ++cls) {
+    int per_cu = c->blocks_per_cu[1][cls];
+    if (cls < CLS_W32) {
+      p.ring[cls] = lane8_ring_chunks(cls, wmax);
+      per_cu = chunked_per_cu(c, cls, sym, p.ring[cls]);
+    }
+    p.blocks[cls] = (int64_t)tuned_per_cu(c, cls, per_cu) * c->num_cu;
+    if (cls < CLS_W32) {
+      p.qt_off[cls] = p.qt_words;
+      p.qt_words += (size_t)p.blocks[cls] * lane8_qtile_words(cls);
+    }
+  }
+  p.ring[NCLS] = lane8_ring_chunks(R1CLS, wmax);
+  p.blocks[NCLS] = (int64_t)chunked_per_cu(c, R1CLS, sym, p.ring[NCLS]) * c->num_cu;
+  p.qt_off[NCLS] = p.qt_words;
+  p.qt_words += (size_t)p.blocks[NCLS] * lane8_qtile_words(R1CLS);
+  p.blocks[NCLS + 1] = (int64_t)c->blocks_per_cu[1][R2CLS] * c->num_cu;
+  return p;
+}
+
+// Every step of the batched path, with no host wait in between.  The
+// classes run concurrently on the side streams (8-bit widest first, then
+// 16-bit, 32-bit), so that one class's tail overlaps the next class's
+// work; the long class and the two reruns follow on the main stream.
+int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan& p,
+                    bool sym, hipStream_t s) {
+  int rc;
+  uint32_t* qt = (uint32_t*)c->qtiles.p;
+  int2* gbuf = (int2*)c->longbuf.p;
+  uint8_t* gq = (uint8_t*)(gbuf + (size_t)LONG_SLOTS * LONG_SLOT_COLS);
+  Status* st = w.st;
+  const bool ev = !c->graph_call;
+  if (ev) HIPCHK(hipEventRecord(c->ev[0], s));
+  enqueue_prep_bin(c, a, w, s);
+  HIPCHK(hipGetLastError());
+  if (ev) HIPCHK(hipEventRecord(c->ev[1], s));
+  if (ev) HIPCHK(hipEventRecord(c->ev[2], s));
+  c->n_launch = 0;
+  HIPCHK(hipEventRecord(c->fork_ev, s));
+  const int nside = c->tune.nside;
+  for (int k = 0; k < nside; ++k) HIPCHK(hipStreamWaitEvent(c->side[k], c->fork_ev, 0));
+  int order[NCLS], no = 0;
+  for (int cls = CLS_W16 - 1; cls >= CLS_L8; --cls) order[no++] = cls;
+  for (int cls = CLS_W16; cls < CLS_LONG; ++cls) order[no++] = cls;
+  for (int oi = 0; oi < no; ++oi) {
+    const int cls = order[oi];
+    hipStream_t ls = c->side[oi % nside];
+    if ((rc = begin_launch(c, cls, ls))) return rc;
+    // 8-bit overflows go to the first rerun list, 16-bit ones to the second
+    launch_lane(cls, true, (unsigned)p.blocks[cls], w.desc, w.cls_range + 2 * cls, a.q,
+                a.t, c->d_kp, a.out, a.diag, w.ctr + cls, st,
+                cls < CLS_W32 ? qt + p.qt_off[cls] : nullptr, cls < CLS_W16 ? w.ovf : w.ovf2,
+                cls < CLS_W16 ? &st->ovf_range[1] : &st->ovf2_range[1], p.ring[cls], sym,
+                &st->cls_cells[cls], ls);
+    if ((rc = end_launch(c, ls))) return rc;
+  }
+  for (int k = 0; k < nside; ++k) {
+    HIPCHK(hipEventRecord(c->join_ev[k], c->side[k]));
+    HIPCHK(hipStreamWaitEvent(s, c->join_ev[k], 0));
+  }
+  if ((rc = begin_launch(c, CLS_LONG, s))) return rc;
+  launch_long(w.desc, w.cls_range + 2 * CLS_LONG, a.q, a.t, c->d_kp, a.out, a.diag,
+              w.ctr + CLS_LONG, gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
+  if ((rc = end_launch(c, s))) return rc;
+  if ((rc = begin_launch(c, NCLS, s))) return rc;
+  launch_lane(R1CLS, true, (unsigned)p.blocks[NCLS], w.ovf, st->ovf_range, a.q, a.t,
+              c->d_kp, a.out, a.diag, w.ctr + NCLS, st, qt + p.qt_off[NCLS], w.ovf2,
+              &st->ovf2_range[1], p.ring[NCLS], sym, &st->cls_cells[NCLS], s);
+  if ((rc = end_launch(c, s))) return rc;
+  if ((rc = begin_launch(c, NCLS + 1, s))) return rc;
+  launch_lane(R2CLS, true, (unsigned)p.blocks[NCLS + 1], w.ovf2, st->ovf2_range, a.q, a.t,
+              c->d_kp, a.out, a.diag, w.ctr + NCLS + 1, st, nullptr, nullptr, nullptr, 0,
+              false, &st->cls_cells[NCLS + 1], s);
+  if ((rc = end_launch(c, s))) return rc;
+  HIPCHK(hipGetLastError());
+  if (ev) HIPCHK(hipEventRecord(c->ev[3], s));
+  return BSW_OK;
+}
+
+// Tuned shapes are cached per device, band limit, gap symmetry and lane
+// width floor in a small JSON file, one entry per line:
+//   "gfx950:cu256:w100:sym1:mb0": {"nside": 4, "occ8": 100, "spec16": 1, "ms": 57.1},
+std::string tune_key(const bsw_ctx* c, int wmax, bool sym) {
+  char k[160];
+  std::snprintf(k, sizeof k, "%s:cu%d:w%d:sym%d:mb%d", c->dev_name, c->num_cu, wmax,
+                sym ? 1 : 0, c->opts.min_lane_bits);
+  return k;
+}
+
+std::vector<std::pair<std::string, std::string>> cache_read(const char* path) {
+  std::vector<std::pair<std::string, std::string>> e;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return e;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* a = std::strchr(line, '"');
+    const char* b = a ? std::strchr(a + 1, '"') : nullptr;
+    const char* v = b ? std::strchr(b, '{') : nullptr;
+    const char* z = v ? std::strchr(v, '}') : nullptr;
+    if (a && b && v && z) e.emplace_back(std::string(a + 1, b), std::string(v, z + 1));
+  }
+  std::fclose(f);
+  return e;
+}
+
+bool cache_lookup(const char* path, const std::string& key, Tune* t) {
+  for (auto& kv : cache_read(path)) {
+    if (kv.first != key) continue;
+    Tune x;
+    double ms = 0;
+    if (std::sscanf(kv.second.c_str(), "{\"nside\": %d, \"occ8\": %d, \"spec16\": %d, \"ms\": %lf}",
+                    &x.nside, &x.occ8, &x.spec16, &ms) != 4)
+      return false;
+    if ((x.nside != 1 && x.nside != 2 && x.nside != 4) || x.occ8 < 1 || x.occ8 > 100 ||
+        (x.spec16 != 0 && x.spec16 != 1))
+      return false;
+    *t = x;
+    return true;
+  }
+  return false;
+}
+
+int cache_store(const char* path, const std::string& key, const Tune& t, double ms) {
+  auto e = cache_read(path);
+  char v[160];
+  std::snprintf(v, sizeof v, "{\"nside\": %d, \"occ8\": %d, \"spec16\": %d, \"ms\": %.3f}",
+                t.nside, t.occ8, t.spec16, ms);
+  bool found = false;
+  for (auto& kv : e)
+    if (kv.first == key) {
+      kv.second = v;
+      found = true;
+    }
+  if (!found) e.emplace_back(key, v);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return fail(BSW_EINVAL, "cannot write the tune cache %s", tmp.c_str());
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < e.size(); ++i)
+    std::fprintf(f, " \"%s\": %s%s\n", e[i].first.c_str(), e[i].second.c_str(),
+                 i + 1 < e.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), path) != 0)
+    return fail(BSW_EINVAL, "cannot write the tune cache %s", path);
+  return BSW_OK;
+}
+
+// Shapes for this call's scoring: from the cache when it has an entry.
+void pick_tune(bsw_ctx* c, int wmax, bool sym) {
+  if (!c->opts.tune_cache) return;
+  const std::string key = tune_key(c, wmax, sym);
+  if (key == c->tune_key) return;
+  c->tune_key = key;
+  Tune t;
+  if (cache_lookup(c->opts.tune_cache, key, &t)) c->tune = t;
+}
+
+// Batched path: plan, make sure every buffer exists, then run the steps
+// eagerly or as a graph.  The graph is captured on the first call with a
+// given set of pointers and shapes and replayed while they stay the same;
+// the scoring table is uploaded outside it, before every replay.
+int run_batched(bsw_ctx* c, const Args& a, hipStream_t s) {
+  int wmax;
+  bool sym;
+  scan_params(c, a.n_params, &wmax, &sym);
+  pick_tune(c, wmax, sym);
+  const Layout L = layout_for(a.n);
+  int rc;
+  if ((rc = c->ws.ensure(L.total))) return rc;
+  const BatchedPlan p = plan_batched(c, wmax, sym);
+  if ((rc = c->qtiles.ensure(p.qt_words * 4))) return rc;
+  if ((rc = c->longbuf.ensure((size_t)LONG_SLOTS * LONG_SLOT_COLS * (sizeof(int2) + 1))))
+    return rc;
+  const Work w = carve((char*)c->ws.p, L);
+  c->last_st = w.st;
+  HIPCHK(hipMemcpyAsync(c->d_kp, c->h_kp, sizeof(KParams) * a.n_params,
+                        hipMemcpyHostToDevice, s));
+  c->graph_call = !c->opts.no_graph;
+  if (!c->graph_call) return enqueue_batched(c, a, w, p, sym, s);
+  GraphKey key;
+  key.a = a;
+  key.s = s;
+  key.ws = c->ws.p;
+  key.qt = c->qtiles.p;
+  key.lb = c->longbuf.p;
+  key.wmax = wmax;
+  key.sym = sym;
+  key.tune = c->tune;
+  if (!c->gexec || !same_key(key, c->gkey)) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_batched(c, a, w, p, sym, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess)
+      return fail(BSW_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      c->gexec = nullptr;
+      return fail(BSW_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    c->gkey = key;
+    c->n_graph_launch = c->n_launch;
+  }
+  c->n_launch = c->n_graph_launch;
+  HIPCHK(hipEventRecord(c->ev[0], s));
+  HIPCHK(hipGraphLaunch(c->gexec, s));
+  HIPCHK(hipEventRecord(c->ev[3], s));
+  return BSW_OK;
+}
+
+// Plain path: prepare + bin, wait for the class counts, then one ordinary
+// launch per non-empty class on the caller's stream, in order.
+int run_plain(bsw_ctx* c, const Args& a, hipStream_t s) {
+  int wmax;
+  bool sym;
+  scan_params(c, a.n_params, &wmax, &sym);
+  const Layout L = layout_for(a.n);
   int rc = c->ws.ensure(L.total);
   if (rc) return rc;
-  char* base = (char*)c->ws.p;
-  uint32_t* hist = (uint32_t*)(base + L.hist);
-  Status* st = (Status*)(base + L.status);
-  uint32_t* ctr = (uint32_t*)(base + L.ctr);
-  uint32_t* cursor = (uint32_t*)(base + L.cursor);
-  long long* cls_range = (long long*)(base + L.cls_range);
-  PairDesc* ovf = (PairDesc*)(base + L.ovf);
-  PairDesc* ovf2 = (PairDesc*)(base + L.ovf2);
-  uint32_t* keys = (uint32_t*)(base + L.keys);
-  PairDesc* desc = (PairDesc*)(base + L.desc);
-
-  HIPCHK(hipMemcpyAsync(c->d_kp, c->h_kp, sizeof(KParams) * n_params,
+  const Work w = carve((char*)c->ws.p, L);
+  Status* st = w.st;
+  c->last_st = st;
+  c->graph_call = false;
+  HIPCHK(hipMemcpyAsync(c->d_kp, c->h_kp, sizeof(KParams) * a.n_params,
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipEventRecord(c->ev[0], s));
-  launch_fill((uint32_t*)(base + L.zero_beg), (int64_t)((L.zero_end - L.zero_beg) / 4), s);
-  launch_prep(n, q, t, q_off, t_off, h0, pid, n_params, c->d_kp, c->opts.min_lane_bits,
-              c->opts.force_mode, keys, hist, st, s);
-  launch_codes(q, q_off, n, st, s);
-  launch_codes(t, t_off, n, st, s);
-  launch_scan(hist, cursor, cls_range, s);
-  launch_scatter(n, q_off, t_off, h0, pid, keys, cursor, desc, st, s);
+  enqueue_prep_bin(c, a, w, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(c->ev[1], s));
   HIPCHK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(c->h_cls, cls_range, sizeof(long long) * 2 * NCLS,
+  HIPCHK(hipMemcpyAsync(c->h_cls, w.cls_range, sizeof(long long) * 2 * NCLS,
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (c->h_status->bad)
-    return fail(BSW_EINVAL, "pair %llu is invalid (lengths, h0, param_id or a code > 4)",
-                ~(unsigned long long)c->h_status->first_bad_inv);
-
-  const bool persist = c->opts.path != BSW_PATH_PLAIN;
-  // occupancy of a chunked class with a given ring (cached per context)
-  auto chunked_per_cu = [&](int cls, int rg) {
-    int& occ = c->occc[sym ? 1 : 0][cls][rg];
-    if (!occ) occ = lane_blocks_per_cu(cls, sym, (size_t)rg * lane_chunk_row_bytes(cls));
-    return occ;
-  };
-  // grid of every lane class, and the query-tile space of the chunked ones;
-  // the 16-bit rerun of 8-bit overflows gets the last query-tile region
-  const int r1cls = CLS_W16 + NLW - 1, r2cls = CLS_W32 + NLW - 1;
+  if (c->h_status->bad) return BSW_OK;  // reported when the call completes
   int64_t blocks[NCLS] = {};
   int ring[NCLS] = {};
   size_t qt_off[NCLS] = {}, qt_words = 0;
@@ -292,126 +636,155 @@ int run_pipeline(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
     const int64_t count = c->h_cls[2 * cls + 1];
     if (count <= 0) continue;
     const int wpb = lane_waves_per_block(cls);
-    const int64_t tiles = (count + 63) / 64;
-    blocks[cls] = (tiles + wpb - 1) / wpb;
-    int per_cu = c->blocks_per_cu[1][cls];
+    blocks[cls] = ((count + 63) / 64 + wpb - 1) / wpb;
     if (cls < CLS_W32) {
       ring[cls] = lane8_ring_chunks(cls, wmax);
-      per_cu = chunked_per_cu(cls, ring[cls]);
-    }
-    if (persist) blocks[cls] = std::min(blocks[cls], (int64_t)per_cu * c->num_cu);
-    if (cls < CLS_W32) {
       (cls < CLS_W16 ? any8 : any16) = true;
       qt_off[cls] = qt_words;
       qt_words += (size_t)blocks[cls] * lane8_qtile_words(cls);
     }
   }
-  const int r1ring = lane8_ring_chunks(r1cls, wmax);
-  const int64_t r1blocks = any8 ? (int64_t)chunked_per_cu(r1cls, r1ring) * c->num_cu : 0;
+  const int r1ring = lane8_ring_chunks(R1CLS, wmax);
+  const int64_t r1blocks = any8 ? (int64_t)chunked_per_cu(c, R1CLS, sym, r1ring) * c->num_cu : 0;
   const size_t r1qt = qt_words;
-  qt_words += (size_t)r1blocks * lane8_qtile_words(r1cls);
+  qt_words += (size_t)r1blocks * lane8_qtile_words(R1CLS);
   if (qt_words && (rc = c->qtiles.ensure(qt_words * 4))) return rc;
   uint32_t* qt = (uint32_t*)c->qtiles.p;
-  c->n_dp_launches = 0;
   c->n_launch = 0;
   HIPCHK(hipEventRecord(c->ev[2], s));
-  // launch bracketing: start/end events on the launch's stream
-  auto begin_launch = [&](int cls, hipStream_t ls) -> int {
-    c->lcls[c->n_launch] = cls;
-    HIPCHK(hipEventRecord(c->lev0[c->n_launch], ls));
-    return BSW_OK;
-  };
-  auto end_launch = [&](hipStream_t ls) -> int {
-    HIPCHK(hipEventRecord(c->lev[c->n_launch], ls));
-    ++c->n_launch;
-    ++c->n_dp_launches;
-    return BSW_OK;
-  };
-  // batched path: the classes run concurrently on side streams, widest
-  // first, so that one class's tail overlaps the next class's work; the
-  // reruns wait for all of them.  Plain path: one stream, in order.
-  int nside_used = 0;
-  if (persist) {
-    HIPCHK(hipEventRecord(c->fork_ev, s));
-    for (int k = 0; k < bsw_ctx::NSIDE; ++k) HIPCHK(hipStreamWaitEvent(c->side[k], c->fork_ev, 0));
-  }
-  int order[NCLS], no = 0;
-  for (int cls = CLS_W16 - 1; cls >= CLS_L8; --cls) order[no++] = cls;   // 8-bit, widest first
+  int order[NCLS], no = 0;  // same order as the batched path
+  for (int cls = CLS_W16 - 1; cls >= CLS_L8; --cls) order[no++] = cls;
   for (int cls = CLS_W16; cls < CLS_LONG; ++cls) order[no++] = cls;
   for (int oi = 0; oi < no; ++oi) {
     const int cls = order[oi];
     if (blocks[cls] <= 0) continue;
-    hipStream_t ls = persist ? c->side[nside_used++ % bsw_ctx::NSIDE] : s;
-    if ((rc = begin_launch(cls, ls))) return rc;
-    // 8-bit overflows go to the first rerun list, 16-bit ones to the second
-    launch_lane(cls, persist, (unsigned)blocks[cls], desc, cls_range + 2 * cls, q, t,
-                c->d_kp, out, diag, ctr + cls, st, qt ? qt + qt_off[cls] : nullptr,
-                cls < CLS_W16 ? ovf : ovf2,
+    if ((rc = begin_launch(c, cls, s))) return rc;
+    launch_lane(cls, false, (unsigned)blocks[cls], w.desc, w.cls_range + 2 * cls, a.q, a.t,
+                c->d_kp, a.out, a.diag, w.ctr + cls, st, qt ? qt + qt_off[cls] : nullptr,
+                cls < CLS_W16 ? w.ovf : w.ovf2,
                 cls < CLS_W16 ? &st->ovf_range[1] : &st->ovf2_range[1], ring[cls], sym,
-                &st->cls_cells[cls], ls);
-    if ((rc = end_launch(ls))) return rc;
-  }
-  if (persist) {
-    for (int k = 0; k < bsw_ctx::NSIDE; ++k) {
-      HIPCHK(hipEventRecord(c->join_ev[k], c->side[k]));
-      HIPCHK(hipStreamWaitEvent(s, c->join_ev[k], 0));
-    }
+                &st->cls_cells[cls], s);
+    if ((rc = end_launch(c, s))) return rc;
   }
   if (c->h_cls[2 * CLS_LONG + 1] > 0) {
-    const size_t need = (size_t)LONG_SLOTS * LONG_SLOT_COLS * (sizeof(int2) + 1);
-    rc = c->longbuf.ensure(need);
+    rc = c->longbuf.ensure((size_t)LONG_SLOTS * LONG_SLOT_COLS * (sizeof(int2) + 1));
     if (rc) return rc;
     int2* gbuf = (int2*)c->longbuf.p;
     uint8_t* gq = (uint8_t*)(gbuf + (size_t)LONG_SLOTS * LONG_SLOT_COLS);
-    if ((rc = begin_launch(CLS_LONG, s))) return rc;
-    launch_long(desc, cls_range + 2 * CLS_LONG, q, t, c->d_kp, out, diag, ctr + CLS_LONG,
-                gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
-    if ((rc = end_launch(s))) return rc;
+    if ((rc = begin_launch(c, CLS_LONG, s))) return rc;
+    launch_long(w.desc, w.cls_range + 2 * CLS_LONG, a.q, a.t, c->d_kp, a.out, a.diag,
+                w.ctr + CLS_LONG, gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
+    if ((rc = end_launch(c, s))) return rc;
   }
-  // reruns: the counts are only known on the device, so the grids are
+  // reruns: their counts are only known on the device, so the grids are
   // persistent and exit at once when their list is empty
   if (any8) {
-    // 16-bit chunked rerun of the pairs the 8-bit kernels could not settle
-    if ((rc = begin_launch(NCLS, s))) return rc;
-    launch_lane(r1cls, true, (unsigned)r1blocks, ovf, st->ovf_range, q, t, c->d_kp, out,
-                diag, ctr + NCLS, st, qt + r1qt, ovf2, &st->ovf2_range[1], r1ring, sym,
-                &st->cls_cells[NCLS], s);
-    if ((rc = end_launch(s))) return rc;
+    if ((rc = begin_launch(c, NCLS, s))) return rc;
+    launch_lane(R1CLS, true, (unsigned)r1blocks, w.ovf, st->ovf_range, a.q, a.t, c->d_kp,
+                a.out, a.diag, w.ctr + NCLS, st, qt + r1qt, w.ovf2, &st->ovf2_range[1],
+                r1ring, sym, &st->cls_cells[NCLS], s);
+    if ((rc = end_launch(c, s))) return rc;
   }
   if (any8 || any16) {
-    // 32-bit rerun of the pairs the 16-bit kernels could not settle
-    if ((rc = begin_launch(NCLS + 1, s))) return rc;
-    launch_lane(r2cls, true, (unsigned)(c->blocks_per_cu[1][r2cls] * c->num_cu), ovf2,
-                st->ovf2_range, q, t, c->d_kp, out, diag, ctr + NCLS + 1, st, nullptr,
-                nullptr, nullptr, 0, false, &st->cls_cells[NCLS + 1], s);
-    if ((rc = end_launch(s))) return rc;
+    if ((rc = begin_launch(c, NCLS + 1, s))) return rc;
+    launch_lane(R2CLS, true, (unsigned)(c->blocks_per_cu[1][R2CLS] * c->num_cu), w.ovf2,
+                st->ovf2_range, a.q, a.t, c->d_kp, a.out, a.diag, w.ctr + NCLS + 1, st,
+                nullptr, nullptr, nullptr, 0, false, &st->cls_cells[NCLS + 1], s);
+    if ((rc = end_launch(c, s))) return rc;
   }
-  HIPCHK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(c->ev[3], s));
   return BSW_OK;
 }
 
+// Enqueue a whole call on stream s, then the copy of its status to the
+// host.  All pointers are device pointers.
+int run_pipeline(bsw_ctx* c, const Args& a, hipStream_t s) {
+  int rc = c->opts.path == BSW_PATH_PLAIN ? run_plain(c, a, s) : run_batched(c, a, s);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(c->h_status, c->last_st, sizeof(Status), hipMemcpyDeviceToHost, s));
+  return BSW_OK;
+}
+
 // device time of the last call: prepare+bin and DP kernels (the host wait
 // between the two is not counted)
+// (a graph replay has only its whole span: the steps inside carry no
+// events).  A failed query is cleared so that it does not linger as the
+// thread's last HIP error.
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    ms = 0;
+  }
+  return ms;
+}
+
 void record_timing(bsw_ctx* c) {
-  float a = 0, b = 0;
-  if (hipEventElapsedTime(&a, c->ev[0], c->ev[1]) == hipSuccess &&
-      hipEventElapsedTime(&b, c->ev[2], c->ev[3]) == hipSuccess) {
+  c->timing[3] = c->n_launch;
+  if (c->graph_call) {
+    c->timing[0] = elapsed(c->ev[0], c->ev[3]);
+    c->timing[1] = c->timing[2] = 0;
+  } else {
+    const float a = elapsed(c->ev[0], c->ev[1]), b = elapsed(c->ev[2], c->ev[3]);
     c->timing[0] = (double)a + b;
     c->timing[1] = a;
     c->timing[2] = b;
-    c->timing[3] = c->n_dp_launches;
   }
   for (int k = 0; k < c->n_launch; ++k) {
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, c->lev0[k], c->lev[k]) != hipSuccess) ms = 0;
-    c->lms[k] = ms;
+    c->lms[k] = c->graph_call ? 0.0 : elapsed(c->lev0[k], c->lev[k]);
     c->lcells[k] = c->h_status->cls_cells[c->lcls[k]];
   }
 }
 
+// After the stream has passed a call: its status (a rejected pair is
+// reported here), then its timing.
+int finish_call(bsw_ctx* c) {
+  if (c->h_status->bad)
+    return fail(BSW_EINVAL, "pair %llu is invalid (lengths, h0, param_id or a code > 4)",
+                ~(unsigned long long)c->h_status->first_bad_inv);
+  record_timing(c);
+  return BSW_OK;
+}
+
 }  // namespace
+
+namespace bsw {
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ctx_set_params(bsw_ctx* c, const bsw_params* params, int32_t n_params) {
+  const int rc = check_params(params, n_params);
+  if (rc) return rc;
+  for (int i = 0; i < n_params; ++i) c->h_kp[i] = to_kparams(params[i]);
+  return BSW_OK;
+}
+
+int ctx_enqueue(bsw_ctx* c, const Args& a, hipStream_t s) {
+  int rc = set_device(c);
+  if (rc) return rc;
+  return run_pipeline(c, a, s);
+}
+
+int ctx_finish(bsw_ctx* c) { return finish_call(c); }
+
+unsigned long long ctx_last_cells(const bsw_ctx* c) {
+  unsigned long long sum = 0;
+  for (int k = 0; k < NCLS + 2; ++k) sum += c->h_status->cls_cells[k];
+  return sum;
+}
+
+hipStream_t ctx_stream(const bsw_ctx* c) { return c->stream; }
+
+}  // namespace bsw
 
 extern "C" {
 
@@ -445,6 +818,9 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
   c->opts = o;
   c->device = o.device;
   c->num_cu = prop.multiProcessorCount;
+  std::snprintf(c->dev_name, sizeof c->dev_name, "%s", prop.gcnArchName);
+  c->budget.limit = o.hbm_budget;
+  for (DevBuf* d : {&c->ws, &c->in, &c->res, &c->longbuf, &c->qtiles}) d->b = &c->budget;
   int rc = BSW_OK;
   if (hipSetDevice(c->device) != hipSuccess ||
       hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -493,6 +869,7 @@ void bsw_ctx_destroy(bsw_ctx* c) {
   c->res.release();
   c->longbuf.release();
   c->qtiles.release();
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->h_kp) (void)hipHostFree(c->h_kp);
   if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->h_cls) (void)hipHostFree(c->h_cls);
@@ -528,7 +905,9 @@ int bsw_extend_batch_device(bsw_ctx* c, int64_t n, const uint8_t* q,
   if ((rc = set_device(c))) return rc;
   for (int i = 0; i < n_params; ++i) c->h_kp[i] = to_kparams(params[i]);
   hipStream_t s = stream ? (hipStream_t)stream : c->stream;
-  rc = run_pipeline(c, n, q, q_off, t, t_off, h0, param_id, n_params, out, diag, s);
+  const Args a = {n, q, q_off, t, t_off, h0, param_id, n_params, out, diag,
+                 nullptr, nullptr, false};
+  rc = run_pipeline(c, a, s);
   if (rc) return rc;
   if (async) {
     c->pending = true;
@@ -536,7 +915,76 @@ int bsw_extend_batch_device(bsw_ctx* c, int64_t n, const uint8_t* q,
     return BSW_OK;
   }
   HIPCHK(hipStreamSynchronize(s));
-  record_timing(c);
+  return finish_call(c);
+}
+
+int bsw_ctx_tune(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
+                 const uint8_t* t, const uint64_t* t_off, const int32_t* h0,
+                 const uint8_t* param_id, const bsw_params* params, int32_t n_params,
+                 bsw_result* out, int32_t reps, double* best_ms) {
+  if (!c) return fail(BSW_EINVAL, "ctx is NULL");
+  if (c->opts.path != BSW_PATH_BATCHED)
+    return fail(BSW_EINVAL, "tuning applies to the batched path");
+  if (n < 1 || n > 0x7fffffffLL) return fail(BSW_EINVAL, "n = %lld out of range", (long long)n);
+  if (reps < 1 || reps > 100) return fail(BSW_EINVAL, "reps must be 1..100");
+  int rc = check_params(params, n_params);
+  if (rc) return rc;
+  if (!q_off || !t_off || !h0 || !out)
+    return fail(BSW_EINVAL, "a required device pointer is NULL");
+  if ((rc = set_device(c))) return rc;
+  for (int i = 0; i < n_params; ++i) c->h_kp[i] = to_kparams(params[i]);
+  int wmax;
+  bool sym;
+  scan_params(c, n_params, &wmax, &sym);
+  const Args a = {n, q, q_off, t, t_off, h0, param_id, n_params, out, nullptr,
+                  nullptr, nullptr, false};
+  std::vector<Tune> cands;
+  for (int ns : {4, 2, 1})
+    for (int occ : {100, 50})
+      for (int sp : {1, 0}) {
+        Tune x;
+        x.nside = ns;
+        x.occ8 = occ;
+        x.spec16 = sp;
+        cands.push_back(x);
+      }
+  // every candidate runs eagerly: one warm-up call, then reps timed calls;
+  // the score is the fastest timed call (device time, first to last step)
+  const int32_t saved = c->opts.no_graph;
+  c->opts.no_graph = 1;
+  Tune best = c->tune;
+  double best_t = 1e300;
+  for (const Tune& x : cands) {
+    c->tune = x;
+    double tmin = 1e300;
+    for (int r = 0; r <= reps && rc == BSW_OK; ++r) {
+      rc = run_pipeline(c, a, c->stream);
+      if (rc == BSW_OK && hipStreamSynchronize(c->stream) != hipSuccess)
+        rc = fail(BSW_EDEVICE, "stream synchronisation failed");
+      if (rc == BSW_OK) rc = finish_call(c);
+      if (rc == BSW_OK && r > 0) tmin = std::min(tmin, c->timing[0]);
+    }
+    if (rc) break;
+    if (tmin < best_t) {
+      best_t = tmin;
+      best = x;
+    }
+  }
+  c->opts.no_graph = saved;
+  if (rc) return rc;
+  c->tune = best;
+  c->tune_key = tune_key(c, wmax, sym);
+  if (best_ms) *best_ms = best_t;
+  if (c->opts.tune_cache && (rc = cache_store(c->opts.tune_cache, c->tune_key, best, best_t)))
+    return rc;
+  return BSW_OK;
+}
+
+int bsw_ctx_tune_info(bsw_ctx* c, int32_t out3[3]) {
+  if (!c || !out3) return fail(BSW_EINVAL, "NULL argument");
+  out3[0] = c->tune.nside;
+  out3[1] = c->tune.occ8;
+  out3[2] = c->tune.spec16;
   return BSW_OK;
 }
 
@@ -545,8 +993,7 @@ int bsw_ctx_wait(bsw_ctx* c) {
   if (!c->pending) return BSW_OK;
   c->pending = false;
   HIPCHK(hipStreamSynchronize(c->pending_stream));
-  record_timing(c);
-  return BSW_OK;
+  return finish_call(c);
 }
 
 int bsw_ctx_last_kernels(bsw_ctx* c, int32_t* cls, int64_t* cells, double* ms,
@@ -633,20 +1080,29 @@ int bsw_extend_batch(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_
   if (param_id)
     HIPCHK(hipMemcpyAsync(din + o_pid, param_id, (size_t)n, hipMemcpyHostToDevice, s));
   for (int i = 0; i < n_params; ++i) c->h_kp[i] = to_kparams(params[i]);
-  rc = run_pipeline(c, n, (const uint8_t*)(din + o_q), (const uint64_t*)(din + o_qo),
-                    (const uint8_t*)(din + o_t), (const uint64_t*)(din + o_to),
-                    (const int32_t*)(din + o_h0),
-                    param_id ? (const uint8_t*)(din + o_pid) : nullptr, n_params,
-                    (bsw_result*)(dres + o_out), diag ? (bsw_diag*)(dres + o_diag) : nullptr,
-                    s);
+  const Args a = {n,
+                 (const uint8_t*)(din + o_q),
+                 (const uint64_t*)(din + o_qo),
+                 (const uint8_t*)(din + o_t),
+                 (const uint64_t*)(din + o_to),
+                 (const int32_t*)(din + o_h0),
+                 param_id ? (const uint8_t*)(din + o_pid) : nullptr,
+                 n_params,
+                 (bsw_result*)(dres + o_out),
+                 diag ? (bsw_diag*)(dres + o_diag) : nullptr,
+                 nullptr,
+                 nullptr,
+                 false};
+  rc = run_pipeline(c, a, s);
   if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(s));
+  if ((rc = finish_call(c))) return rc;
   HIPCHK(hipMemcpyAsync(out, dres + o_out, sizeof(bsw_result) * (size_t)n,
                         hipMemcpyDeviceToHost, s));
   if (diag)
     HIPCHK(hipMemcpyAsync(diag, dres + o_diag, sizeof(bsw_diag) * (size_t)n,
                           hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  record_timing(c);
   return BSW_OK;
 }
 

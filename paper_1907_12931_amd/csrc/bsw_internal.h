@@ -67,6 +67,18 @@ struct Status {
   unsigned long long cls_cells[32];  // band cells per class (+ rerun slot)
 };
 
+// One request of a serving batch (see k_assemble).
+struct ReqSlice {
+  long long base;            // first batch pair of the request
+  long long n;               // its pairs
+  unsigned long long q_at;   // byte offset of its query bytes from the base
+  unsigned long long t_at;   // byte offset of its target bytes from the base
+  const uint64_t* q_off;     // its n + 1 query offsets (device)
+  const uint64_t* t_off;     // its n + 1 target offsets (device)
+  const int32_t* h0;         // its n seed scores (device)
+  const uint8_t* pid;        // its n scoring-set indices (device) or null
+};
+
 constexpr int LONG_SLOTS = 256;          // waves running the long class
 constexpr int LONG_SLOT_COLS = 65536;    // row-buffer entries per slot
 

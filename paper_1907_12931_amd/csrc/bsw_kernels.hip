@@ -96,19 +96,23 @@ __global__ void k_fill(uint32_t* p, int64_t nwords) {
     p[i] = 0;
 }
 
+// Pair k's sequences are q[q_off[k] .. q_end[k]) and t[t_off[k] .. t_end[k]);
+// for an ordinary batch q_end = q_off + 1 and t_end = t_off + 1.
 __global__ void k_prep(int64_t n, const uint8_t* __restrict__ q,
                        const uint8_t* __restrict__ t,
                        const uint64_t* __restrict__ q_off,
+                       const uint64_t* __restrict__ q_end,
                        const uint64_t* __restrict__ t_off,
+                       const uint64_t* __restrict__ t_end,
                        const int32_t* __restrict__ h0,
                        const uint8_t* __restrict__ pid, int n_params,
                        const KParams* __restrict__ kp, int min_bits,
-                       int force_mode, uint32_t* __restrict__ keys,
+                       int spec16, uint32_t* __restrict__ keys,
                        uint32_t* __restrict__ hist, Status* st) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t qo = q_off[k], qe = q_off[k + 1];
-    const uint64_t to = t_off[k], te = t_off[k + 1];
+    const uint64_t qo = q_off[k], qe = q_end[k];
+    const uint64_t to = t_off[k], te = t_end[k];
     const int p = pid ? pid[k] : 0;
     const int hh = h0[k];
     const bool ok = qe >= qo && te >= to && qe - qo <= BSW_MAX_LEN &&
@@ -127,10 +131,10 @@ __global__ void k_prep(int64_t n, const uint8_t* __restrict__ q,
     int wd = U <= 255 ? W8 : (U <= 65535 ? W16 : W32);
     if (min_bits >= 16 && wd < W16) wd = W16;
     if (min_bits >= 32) wd = W32;
-    (void)force_mode;
     // 16-bit pairs start at 8 bits when the seed itself leaves room
     const int slack = P.amax - P.oe_del > 0 ? P.amax - P.oe_del : 0;
-    const bool spec8 = wd == W8 || (wd == W16 && min_bits < 16 && hh + slack <= 255);
+    const bool spec8 =
+        wd == W8 || (spec16 && wd == W16 && min_bits < 16 && hh + slack <= 255);
     int cls, cap;
     if (ql > 256) {
       cls = CLS_LONG;
@@ -265,7 +269,9 @@ k_scan(const uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor,
 }
 
 __global__ void k_scatter(int64_t n, const uint64_t* __restrict__ q_off,
+                          const uint64_t* __restrict__ q_end,
                           const uint64_t* __restrict__ t_off,
+                          const uint64_t* __restrict__ t_end,
                           const int32_t* __restrict__ h0,
                           const uint8_t* __restrict__ pid,
                           const uint32_t* __restrict__ keys,
@@ -279,14 +285,41 @@ __global__ void k_scatter(int64_t n, const uint64_t* __restrict__ q_off,
     PairDesc d;
     d.qo = q_off[k];
     d.to = t_off[k];
-    d.ql = (uint16_t)(q_off[k + 1] - d.qo);
-    d.tl = (uint16_t)(t_off[k + 1] - d.to);
+    d.ql = (uint16_t)(q_end[k] - d.qo);
+    d.tl = (uint16_t)(t_end[k] - d.to);
     d.h0 = h0[k];
     d.idx = (uint32_t)k;
     d.pid = pid ? pid[k] : 0;
     d.cls = (uint8_t)(key >> KEY_SUB_BITS);
     d.pad_[0] = d.pad_[1] = 0;
     desc[pos] = d;
+  }
+}
+
+// Serving: gather the pairs of several resident requests into one batch.
+// Request r covers batch pairs [tab[r].base, tab[r].base + tab[r].n); its
+// sequence bytes sit at byte offsets q_at / t_at from the common base and
+// its offset arrays are the caller's, taken relative to their first entry.
+__global__ void k_assemble(const ReqSlice* __restrict__ tab, int m, int64_t n,
+                           uint64_t* __restrict__ qb, uint64_t* __restrict__ qe,
+                           uint64_t* __restrict__ tb, uint64_t* __restrict__ te,
+                           int32_t* __restrict__ h0, uint8_t* __restrict__ pid) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int a = 0, b = m - 1;  // last request with base <= g
+    while (a < b) {
+      const int c = (a + b + 1) >> 1;
+      if (tab[c].base <= g) a = c; else b = c - 1;
+    }
+    const ReqSlice& r = tab[a];
+    const int64_t i = g - r.base;
+    const uint64_t q0 = r.q_off[0], t0 = r.t_off[0];
+    qb[g] = r.q_at + (r.q_off[i] - q0);
+    qe[g] = r.q_at + (r.q_off[i + 1] - q0);
+    tb[g] = r.t_at + (r.t_off[i] - t0);
+    te[g] = r.t_at + (r.t_off[i + 1] - t0);
+    h0[g] = r.h0[i];
+    pid[g] = r.pid ? r.pid[i] : 0;
   }
 }
 
@@ -1003,13 +1036,15 @@ void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s) {
 }
 
 void launch_prep(int64_t n, const uint8_t* q, const uint8_t* t, const uint64_t* q_off,
-                 const uint64_t* t_off, const int32_t* h0, const uint8_t* pid,
-                 int n_params, const KParams* kp, int min_bits, int force_mode,
-                 uint32_t* keys, uint32_t* hist, Status* st, hipStream_t s) {
+                 const uint64_t* q_end, const uint64_t* t_off, const uint64_t* t_end,
+                 const int32_t* h0, const uint8_t* pid, int n_params, const KParams* kp,
+                 int min_bits, int spec16, uint32_t* keys, uint32_t* hist, Status* st,
+                 hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_prep, dim3((unsigned)blocks), dim3(256), 0, s, n, q, t, q_off,
-                     t_off, h0, pid, n_params, kp, min_bits, force_mode, keys, hist, st);
+                     q_end, t_off, t_end, h0, pid, n_params, kp, min_bits, spec16, keys,
+                     hist, st);
 }
 
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
@@ -1022,14 +1057,23 @@ void launch_scan(const uint32_t* hist, uint32_t* cursor, long long* cls_range,
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, cursor, cls_range);
 }
 
-void launch_scatter(int64_t n, const uint64_t* q_off, const uint64_t* t_off,
-                    const int32_t* h0, const uint8_t* pid, const uint32_t* keys,
-                    uint32_t* cursor, PairDesc* desc, const Status* st,
-                    hipStream_t s) {
+void launch_scatter(int64_t n, const uint64_t* q_off, const uint64_t* q_end,
+                    const uint64_t* t_off, const uint64_t* t_end, const int32_t* h0,
+                    const uint8_t* pid, const uint32_t* keys, uint32_t* cursor,
+                    PairDesc* desc, const Status* st, hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, n, q_off,
-                     t_off, h0, pid, keys, cursor, desc, st);
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, n, q_off, q_end,
+                     t_off, t_end, h0, pid, keys, cursor, desc, st);
+}
+
+void launch_assemble(const ReqSlice* tab, int m, int64_t n, uint64_t* qb, uint64_t* qe,
+                     uint64_t* tb, uint64_t* te, int32_t* h0, uint8_t* pid, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(256), 0, s, tab, m, n, qb, qe,
+                     tb, te, h0, pid);
 }
 
 void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,

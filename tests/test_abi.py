@@ -45,3 +45,22 @@ def test_params_layout():
     import oracle
     assert ctypes.sizeof(bsw.Params) == 56 == ctypes.sizeof(oracle.Params)
     assert bsw.RESULT_DTYPE.itemsize == 24 and bsw.DIAG_DTYPE.itemsize == 16
+
+
+def test_server_without_gpu_gives_edevice():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_1907_12931_amd import bsw, synth
+    with pytest.raises(bsw.BswError) as ei:
+        bsw.Server([synth.BWA_DEFAULT])
+    assert ei.value.code == bsw.EDEVICE
+
+
+def test_struct_layouts_match_header():
+    """The binding's ctypes mirrors have the header's sizes and offsets."""
+    from paper_1907_12931_amd import bsw
+    assert ctypes.sizeof(bsw.ServerOpts) == 32
+    assert bsw.ServerOpts.max_batch_pairs.offset == 8
+    assert ctypes.sizeof(bsw.ServerReport) == 6 * 8 + 9 * 8
+    assert bsw.CtxOpts.no_graph.offset == 32

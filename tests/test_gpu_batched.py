@@ -1,0 +1,134 @@
+"""Batched path: the pipeline captured as a HIP graph must give the same
+results as the same steps enqueued eagerly and as the oracle, on every
+replay, after pointer or shape changes (recapture) and after scoring
+changes (uploaded outside the graph).  All calls go through the C ABI.
+"""
+import numpy as np
+import pytest
+
+from paper_1907_12931_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("score", "qle", "tle", "gtle", "gscore", "max_off")
+
+
+@pytest.fixture(scope="module")
+def bsw():
+    from paper_1907_12931_amd import bsw as m
+    return m
+
+
+def _same(got, want, label):
+    for f in FIELDS:
+        bad = np.nonzero(got[f] != want[f])[0]
+        assert len(bad) == 0, f"{label}: {f} differs at {bad[:5]}"
+
+
+def test_graph_replays_match_eager_and_oracle(oracle_lib, bsw):
+    import torch
+    b = synth.batched_mix(n=120_000, seed=21)
+    n = len(b["h0"])
+    want, wdiag = oracle_lib.extend_batch(b, b["scorings"])
+    dev = bsw.to_device(b)
+    eager = bsw.Context(graph=False)
+    out_e, diag_e = bsw.alloc_outputs(n, with_diag=True)
+    eager.extend_device(dev, b["scorings"], out_e, diag_e)
+    _same(bsw.outputs_to_numpy(out_e), want, "eager")
+    g = bsw.Context()
+    out, diag = bsw.alloc_outputs(n, with_diag=True)
+    junk = torch.empty(1 << 22, dtype=torch.int32, device="cuda")
+    for rep in range(4):
+        out.fill_(0x5A)
+        diag.fill_(0x5A)
+        junk.add_(rep)  # the program's own work between replays
+        torch.cuda.synchronize()
+        g.extend_device(dev, b["scorings"], out, diag)
+        got, gd = bsw.outputs_to_numpy(out, diag)
+        _same(got, want, f"graph replay {rep}")
+        for f in ("rows", "stop", "cells"):
+            assert np.array_equal(gd[f], wdiag[f]), f"replay {rep}: diag {f}"
+    # cells per launch are reported on replays; times only for the whole
+    # replay (the eager context times every launch)
+    ks = g.last_kernels()
+    assert sum(kc for _, kc, _ in ks) == int(wdiag["cells"].sum())
+    assert g.last_timing()[0] > 0
+    ke = eager.last_kernels()
+    assert [x[:2] for x in ke] == [x[:2] for x in ks]
+    assert max(ms for _, _, ms in ke) > 0
+    g.close()
+    eager.close()
+
+
+def test_graph_recaptures_on_new_shapes_and_buffers(oracle_lib, bsw):
+    g = bsw.Context()
+    batches = [synth.read_scale(n=40_000, seed=31), synth.read_scale(n=25_000, seed=32)]
+    wants = [oracle_lib.extend_batch(x, x["scorings"])[0] for x in batches]
+    devs = [bsw.to_device(x) for x in batches]
+    outs = [bsw.alloc_outputs(len(x["h0"]))[0] for x in batches]
+    for k in (0, 1, 0, 1, 1):
+        outs[k].fill_(0)
+        g.extend_device(devs[k], batches[k]["scorings"], outs[k])
+        _same(bsw.outputs_to_numpy(outs[k]), wants[k], f"batch {k}")
+    g.close()
+
+
+def test_graph_picks_up_new_scoring_values(oracle_lib, bsw):
+    b = synth.read_scale(n=30_000, seed=41)
+    dev = bsw.to_device(b)
+    out, _ = bsw.alloc_outputs(len(b["h0"]))
+    g = bsw.Context()
+    for mm, o in ((-4, 6), (-3, 5), (-4, 6)):
+        sc = [synth.scoring(match=1, mismatch=mm, n_score=-1, o=o, e=1, w=100,
+                            zdrop=100, end_bonus=5)]
+        want, _ = oracle_lib.extend_batch(b, sc)
+        out.fill_(0)
+        g.extend_device(dev, sc, out)
+        _same(bsw.outputs_to_numpy(out), want, f"mismatch {mm} open {o}")
+    g.close()
+
+
+def test_async_graph_call_reports_invalid_pair_at_wait(bsw):
+    b = synth.plain_small(n=300)
+    bad = dict(b)
+    bad["t"] = b["t"].copy()
+    bad["t"][int(b["t_off"][201]) + 1] = 7
+    dev = bsw.to_device(bad)
+    out, _ = bsw.alloc_outputs(300)
+    out.fill_(0x3C)
+    g = bsw.Context()
+    g.extend_device(dev, b["scorings"], out, async_=True)
+    with pytest.raises(bsw.BswError) as ei:
+        g.wait()
+    assert ei.value.code == bsw.EINVAL and "201" in str(ei.value)
+    assert bool((out == 0x3C).all())
+    g.close()
+
+
+def test_autotuner_keeps_results_and_caches_its_choice(oracle_lib, bsw, tmp_path):
+    import json
+    b = synth.batched_mix(n=60_000, seed=61)
+    want, _ = oracle_lib.extend_batch(b, b["scorings"])
+    dev = bsw.to_device(b)
+    out, _ = bsw.alloc_outputs(len(b["h0"]))
+    cache = str(tmp_path / "tune.json")
+    c = bsw.Context(tune_cache=cache)
+    ms, shape = c.tune(dev, b["scorings"], out, reps=1)
+    assert ms > 0 and shape["side_streams"] in (1, 2, 4)
+    _same(bsw.outputs_to_numpy(out), want, "tune call")
+    out.fill_(0)
+    c.extend_device(dev, b["scorings"], out)
+    _same(bsw.outputs_to_numpy(out), want, "after tune")
+    c.close()
+    entries = json.load(open(cache))
+    assert len(entries) == 1
+    (key, val), = entries.items()
+    assert key.startswith("gfx950") and ":w100:" in key
+    assert val["nside"] == shape["side_streams"] and val["occ8"] == shape["occ8_pct"]
+    # a new context takes the cached shape on its first call
+    c2 = bsw.Context(tune_cache=cache)
+    out.fill_(0)
+    c2.extend_device(dev, b["scorings"], out)
+    assert c2.tune_info() == shape
+    _same(bsw.outputs_to_numpy(out), want, "cached shape")
+    c2.close()
