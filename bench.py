@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shapes (skip the autotuner)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain streaming kernel over this many MiB "
                          "(read once, written once): the calibration point for "
@@ -189,7 +191,7 @@ def main():
     def run_path(path, steps, warmup, graph=True):
         ctx = bsw.Context(path=path, graph=graph,
                           tune_cache=tune_cache if path == bsw.PATH_BATCHED else None)
-        if path == bsw.PATH_BATCHED and not tuned:
+        if path == bsw.PATH_BATCHED and not tuned and not args.no_tune:
             # launch shapes from the autotuner, on this batch (untimed)
             ms, shape = ctx.tune(dev, batch["scorings"], out, reps=2)
             tuned.update(shape, tune_best_ms=round(ms, 3))
