@@ -90,7 +90,9 @@ struct DevBuf {
   Budget* b = nullptr;
   int ensure(size_t bytes) {
     if (bytes <= cap) return BSW_OK;
-    const size_t want = std::max(bytes, (size_t)1 << 20);
+    // grow by at least half, so that slowly rising sizes reallocate (and
+    // synchronise the device in hipFree) only a few times
+    const size_t want = std::max(std::max(bytes, cap + cap / 2), (size_t)1 << 20);
     if (b && b->limit && b->used - cap + want > b->limit)
       return fail(BSW_ETOOBIG, "the call needs %zu more device bytes than the context's "
                   "budget of %zu", b->used - cap + want - b->limit, b->limit);
@@ -765,6 +767,22 @@ int ctx_set_params(bsw_ctx* c, const bsw_params* params, int32_t n_params) {
   const int rc = check_params(params, n_params);
   if (rc) return rc;
   for (int i = 0; i < n_params; ++i) c->h_kp[i] = to_kparams(params[i]);
+  return BSW_OK;
+}
+
+int ctx_reserve(bsw_ctx* c, int64_t n, int32_t n_params) {
+  int rc = set_device(c);
+  if (rc) return rc;
+  int wmax;
+  bool sym;
+  scan_params(c, n_params, &wmax, &sym);
+  if ((rc = c->ws.ensure(layout_for(n).total))) return rc;
+  if (c->opts.path == BSW_PATH_BATCHED) {
+    const BatchedPlan p = plan_batched(c, wmax, sym);
+    if ((rc = c->qtiles.ensure(p.qt_words * 4))) return rc;
+    if ((rc = c->longbuf.ensure((size_t)LONG_SLOTS * LONG_SLOT_COLS * (sizeof(int2) + 1))))
+      return rc;
+  }
   return BSW_OK;
 }
 

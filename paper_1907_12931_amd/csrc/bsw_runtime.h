@@ -33,6 +33,9 @@ int set_error(int code, const char* fmt, ...);
 
 // Load a context's scoring table (validated).
 int ctx_set_params(bsw_ctx* c, const bsw_params* params, int32_t n_params);
+// Allocate a context's device buffers for calls of up to n pairs with its
+// current scoring table, so that such calls allocate nothing.
+int ctx_reserve(bsw_ctx* c, int64_t n, int32_t n_params);
 // Enqueue one call on stream s (the context's path), ending with the copy
 // of its status to the host.
 int ctx_enqueue(bsw_ctx* c, const Args& a, hipStream_t s);

@@ -253,7 +253,7 @@ int slot_reserve(Slot& sl, int64_t n, int m) {
     if (sl.dev) (void)hipFree(sl.dev);
     sl.dev = nullptr;
     sl.dev_cap = 0;
-    const size_t want = std::max(need + need / 4, (size_t)1 << 20);
+    const size_t want = std::max(need + need / 2, (size_t)1 << 20);
     SRVCHK(hipMalloc(&sl.dev, want));
     sl.dev_cap = want;
   }
@@ -270,7 +270,7 @@ int slot_reserve(Slot& sl, int64_t n, int m) {
     if (sl.h_res) (void)hipHostFree(sl.h_res);
     sl.h_res = nullptr;
     sl.h_res_cap = 0;
-    const size_t want = std::max(res + res / 4, (size_t)1 << 20);
+    const size_t want = std::max(res + res / 2, (size_t)1 << 20);
     SRVCHK(hipHostMalloc(&sl.h_res, want, 0));
     sl.h_res_cap = want;
   }
@@ -532,6 +532,10 @@ int bsw_server_create(bsw_server** out, const bsw_server_opts* opts,
   for (auto& sl : v->slots) {
     if ((rc = bsw_ctx_create(&sl.ctx, &co))) break;
     if ((rc = ctx_set_params(sl.ctx, params, n_params))) break;
+    // workspaces for a full batch up front: growing them later would free
+    // device memory, which waits for all work on the device
+    if ((rc = ctx_reserve(sl.ctx, o.max_batch_pairs, n_params))) break;
+    if ((rc = slot_reserve(sl, o.max_batch_pairs, 1024))) break;
     sl.s = ctx_stream(sl.ctx);
     if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
       rc = set_error(BSW_EDEVICE, "event creation failed");
