@@ -96,36 +96,104 @@ __global__ void k_fill(uint32_t* p, int64_t nwords) {
     p[i] = 0;
 }
 
-// Pair k's sequences are q[q_off[k] .. q_end[k]) and t[t_off[k] .. t_end[k]);
-// for an ordinary batch q_end = q_off + 1 and t_end = t_off + 1.
-__global__ void k_prep(int64_t n, const uint8_t* __restrict__ q,
-                       const uint8_t* __restrict__ t,
-                       const uint64_t* __restrict__ q_off,
-                       const uint64_t* __restrict__ q_end,
-                       const uint64_t* __restrict__ t_off,
-                       const uint64_t* __restrict__ t_end,
-                       const int32_t* __restrict__ h0,
-                       const uint8_t* __restrict__ pid, int n_params,
-                       const KParams* __restrict__ kp, int min_bits,
-                       int spec16, uint32_t* __restrict__ keys,
-                       uint32_t* __restrict__ hist, Status* st) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t qo = q_off[k], qe = q_end[k];
-    const uint64_t to = t_off[k], te = t_end[k];
-    const int p = pid ? pid[k] : 0;
-    const int hh = h0[k];
-    const bool ok = qe >= qo && te >= to && qe - qo <= BSW_MAX_LEN &&
-                    te - to <= BSW_MAX_LEN && hh >= 1 && hh <= BSW_MAX_H0 &&
-                    p < n_params;
-    if (!ok) {
-      atomicMax(&st->first_bad_inv, ~(unsigned long long)k);
-      atomicOr(&st->bad, 1u);
-      keys[k] = 0xffffffffu;
-      continue;
+// Wave-wide inclusive prefix sum and prefix maximum (lane l gets the
+// result over lanes 0..l).  Every lane must be active.
+__device__ __forceinline__ int wave_prefix_sum(int x) {
+  const int lane = threadIdx.x & 63;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ int wave_prefix_max(int x) {
+  const int lane = threadIdx.x & 63;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x = x > y ? x : y;
+  }
+  return x;
+}
+
+// Estimated rows of a pair for the sort key: walk the main diagonal without
+// gaps from h0 until the running score falls to zero or more than z-drop
+// below its running maximum (Sec. 5.1 (b)); the whole wave walks one pair,
+// 64 positions per step.  Only the order of the pairs depends on it.
+// Returns the stopping row + 1, or INT_MAX if the walk reaches its end.
+__device__ int diagonal_rows(const uint8_t* qs, const uint8_t* ts, int L, int h0,
+                             const KParams& P) {
+  const int lane = threadIdx.x & 63;
+  int base = h0, mx = h0;
+  for (int j0 = 0; j0 < L; j0 += 64) {
+    const int j = j0 + lane;
+    int sc = 0;
+    if (j < L) {
+      const int a = ts[j], bq = qs[j];
+      sc = (int)(int8_t)(__builtin_amdgcn_perm(P.prow[a < 5 ? a : 0][1],
+                                               P.prow[a < 5 ? a : 0][0], bq) & 0xffu);
     }
-    const int ql = (int)(qe - qo), tl = (int)(te - to);
-    const KParams& P = kp[p];
+    const int run = base + wave_prefix_sum(sc);
+    const int rmx = imax(mx, wave_prefix_max(run));
+    const bool stop = j < L && (run <= 0 || (P.zdrop > 0 && rmx - run > P.zdrop));
+    const unsigned long long m = __ballot(stop);
+    if (m) return j0 + __builtin_ctzll(m) + 1;
+    base = __shfl(run, 63, 64);
+    mx = __shfl(rmx, 63, 64);
+  }
+  return 0x7fffffff;  // the walk never stops: no estimate
+}
+
+// Pair k's sequences are q[q_off[k] .. q_end[k]) and t[t_off[k] .. t_end[k]);
+// for an ordinary batch q_end = q_off + 1 and t_end = t_off + 1.  Each wave
+// takes 64 consecutive pairs, one per lane.
+__global__ void __launch_bounds__(256)
+k_prep(int64_t n, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
+       const uint64_t* __restrict__ q_off, const uint64_t* __restrict__ q_end,
+       const uint64_t* __restrict__ t_off, const uint64_t* __restrict__ t_end,
+       const int32_t* __restrict__ h0, const uint8_t* __restrict__ pid, int n_params,
+       const KParams* __restrict__ kp, int min_bits, int spec16,
+       uint32_t* __restrict__ keys, uint32_t* __restrict__ hist, Status* st) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t g = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+       g * 64 < n; g += nwaves) {
+    const int64_t k = g * 64 + lane;
+    bool ok = k < n;
+    uint64_t qo = 0, qe = 0, to = 0, te = 0;
+    int p = 0, hh = 1;
+    if (ok) {
+      qo = q_off[k];
+      qe = q_end[k];
+      to = t_off[k];
+      te = t_end[k];
+      p = pid ? pid[k] : 0;
+      hh = h0[k];
+      ok = qe >= qo && te >= to && qe - qo <= BSW_MAX_LEN && te - to <= BSW_MAX_LEN &&
+           hh >= 1 && hh <= BSW_MAX_H0 && p < n_params;
+      if (!ok) {
+        atomicMax(&st->first_bad_inv, ~(unsigned long long)k);
+        atomicOr(&st->bad, 1u);
+        keys[k] = 0xffffffffu;
+      }
+    }
+    const int ql = ok ? (int)(qe - qo) : 0, tl = ok ? (int)(te - to) : 0;
+    const KParams& P = kp[ok ? p : 0];
+    // longest first inside a class: larger query first, then more rows.
+    // For wide queries the rows are estimated by the diagonal walk, capped
+    // by the band (no row past qlen + w + 1 has a cell): pairs that end
+    // early then share tiles, so the lanes of a tile finish together.
+    int rows_est = imin(tl, ql + band_cap(P, ql) + 1);
+    unsigned long long walk = __ballot(ok && ql > 192 && ql <= 256);
+    while (walk) {
+      const int l = __builtin_ctzll(walk);
+      walk &= walk - 1;
+      const uint64_t wq = __shfl(qo, l, 64), wt = __shfl(to, l, 64);
+      const int wl = imin(__shfl(ql, l, 64), __shfl(tl, l, 64));
+      const int wh = __shfl(hh, l, 64), wp = __shfl(p, l, 64);
+      const int r = diagonal_rows(q + wq, t + wt, wl, wh, kp[wp]);
+      if (lane == l) rows_est = imin(rows_est, r);
+    }
+    if (!ok) continue;
     // bound on every stored H and E of the pair (Sec. 5.4.1 precision)
     const int64_t U = (int64_t)hh + (int64_t)P.amax * (ql < tl ? ql : tl);
     int wd = U <= 255 ? W8 : (U <= 65535 ? W16 : W32);
@@ -151,33 +219,10 @@ __global__ void k_prep(int64_t n, const uint8_t* __restrict__ q,
       cls = (wd == W16 ? CLS_W16 : CLS_W32) + c;
       cap = LW_CAP[c];
     }
-    // longest first inside a class: larger query first, then more rows.
-    // For wide queries the rows are estimated by walking the main
-    // diagonal without gaps (every other position, counted twice) until its
-    // score drops below zero or more than z-drop below its running maximum:
-    // pairs that end early (diverged or dropping) then share tiles, so the
-    // lanes of a tile finish together.  Only the order depends on this.
-    int rows_est = tl;
-    if (ql > 192 && ql <= 256) {
-      const uint8_t* qs = q + qo;
-      const uint8_t* tt = t + to;
-      const int L = ql < tl ? ql : tl;
-      int sc = hh, mx = hh;
-      for (int j = 0; j < L; j += 2) {
-        const int a = tt[j], b = qs[j];
-        sc += 2 * (int)(int8_t)(__builtin_amdgcn_perm(P.prow[a < 5 ? a : 0][1],
-                                                      P.prow[a < 5 ? a : 0][0], b) & 0xffu);
-        mx = sc > mx ? sc : mx;
-        if (sc <= 0 || (P.zdrop > 0 && mx - sc > P.zdrop)) {
-          rows_est = j + 1;
-          break;
-        }
-      }
-    }
     int qq = (int)((int64_t)ql * 64 / (cap + 1));
     int tq = rows_est >> 4;
     qq = qq > 63 ? 63 : qq;
-    tq = tq > 63 ? 63 : tq;
+    tq = tq > 63 ? 63 : (tq < 0 ? 0 : tq);
     const uint32_t key = ((uint32_t)cls << KEY_SUB_BITS) |
                          ((uint32_t)(63 - qq) << 6) | (uint32_t)(63 - tq);
     keys[k] = key;
@@ -550,39 +595,42 @@ struct CellParams {
 };
 template <int WB>
 __device__ __forceinline__ uint32_t cell(int d, int e, int s, int j, int& hl, int& f,
-                                         int& mkey, const CellParams& cp) {
+                                         int& key, const CellParams& cp) {
   const int M = d ? d + s : 0;
   const int h = imax(imax(M, e), f);
   const int en = imax(imax(e - cp.eD, M - cp.oeD), 0);
   const uint32_t r = (uint32_t)hl | ((uint32_t)en << WB);
   hl = h;
-  mkey = imax(mkey, (int)(((uint32_t)h << 9) | (uint32_t)j));
+  key = (int)(((uint32_t)h << 9) | (uint32_t)j);
   f = imax(imax(f - cp.eI, M - cp.oeI), 0);
   return r;
 }
+__device__ __forceinline__ int imax3(int a, int b, int c) { return imax(imax(a, b), c); }
 
 // the four cells of a whole chunk (no masking)
 __device__ __forceinline__ uint2 chunk_cells(const uint2 ch, uint32_t sc, int j0, int& hl,
                                              int& f, int& mkey, const CellParams& cp) {
+  int k0, k1, k2, k3;
   const uint32_t r0 = cell<8>(ch.x & 0xff, (ch.x >> 8) & 0xff, (int)(int8_t)sc, j0, hl, f,
-                              mkey, cp);
+                              k0, cp);
   const uint32_t r1 = cell<8>((ch.x >> 16) & 0xff, ch.x >> 24, (int)(int8_t)(sc >> 8),
-                              j0 + 1, hl, f, mkey, cp);
+                              j0 + 1, hl, f, k1, cp);
   const uint32_t r2 = cell<8>(ch.y & 0xff, (ch.y >> 8) & 0xff, (int)(int8_t)(sc >> 16),
-                              j0 + 2, hl, f, mkey, cp);
+                              j0 + 2, hl, f, k2, cp);
   const uint32_t r3 = cell<8>((ch.y >> 16) & 0xff, ch.y >> 24, (int)(int8_t)(sc >> 24),
-                              j0 + 3, hl, f, mkey, cp);
+                              j0 + 3, hl, f, k3, cp);
+  mkey = imax3(imax3(mkey, k0, k1), k2, k3);
   return make_uint2(r0 | (r1 << 16), r2 | (r3 << 16));
 }
 __device__ __forceinline__ uint4 chunk_cells(const uint4 ch, uint32_t sc, int j0, int& hl,
                                              int& f, int& mkey, const CellParams& cp) {
   uint4 r;
-  r.x = cell<16>(ch.x & 0xffff, ch.x >> 16, (int)(int8_t)sc, j0, hl, f, mkey, cp);
-  r.y = cell<16>(ch.y & 0xffff, ch.y >> 16, (int)(int8_t)(sc >> 8), j0 + 1, hl, f, mkey, cp);
-  r.z = cell<16>(ch.z & 0xffff, ch.z >> 16, (int)(int8_t)(sc >> 16), j0 + 2, hl, f, mkey,
-                 cp);
-  r.w = cell<16>(ch.w & 0xffff, ch.w >> 16, (int)(int8_t)(sc >> 24), j0 + 3, hl, f, mkey,
-                 cp);
+  int k0, k1, k2, k3;
+  r.x = cell<16>(ch.x & 0xffff, ch.x >> 16, (int)(int8_t)sc, j0, hl, f, k0, cp);
+  r.y = cell<16>(ch.y & 0xffff, ch.y >> 16, (int)(int8_t)(sc >> 8), j0 + 1, hl, f, k1, cp);
+  r.z = cell<16>(ch.z & 0xffff, ch.z >> 16, (int)(int8_t)(sc >> 16), j0 + 2, hl, f, k2, cp);
+  r.w = cell<16>(ch.w & 0xffff, ch.w >> 16, (int)(int8_t)(sc >> 24), j0 + 3, hl, f, k3, cp);
+  mkey = imax3(imax3(mkey, k0, k1), k2, k3);
   return r;
 }
 // column cc of a chunk, read and written as a record
@@ -641,7 +689,7 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
   using R = typename CK::R;
   extern __shared__ __align__(16) unsigned char smem[];  // [RC][64] chunk words
   const int lane = threadIdx.x;
-  uint32_t* qt = qtiles + (size_t)blockIdx.x * (CAP / 4 + 3) * 64 + lane;
+  uint32_t* qt = qtiles + (size_t)blockIdx.x * (CAP / 4 + 6) * 64 + lane;
   T* my = (T*)smem + lane;
   unsigned char* myb = smem + lane * CK::BYTES;
   // column x's (H, E) record in this lane's ring
@@ -781,19 +829,24 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         int sa = ring_slot(c, RC);
         int sb = sa + 1 == RC ? 0 : sa + 1;
         T chA = my[sa * 64], chB = my[sb * 64];
+        // query dwords of this step (qA, qB) and of the next (qC, qD): the
+        // tile may sit in L2 or beyond, so its loads get two steps
         uint32_t qA = qt[c * 64], qB = qt[(c + 1) * 64];
+        uint32_t qC = qt[(c + 2) * 64], qD = qt[(c + 3) * 64];
         for (; c + 2 <= cf; c += 2) {
           const int sa2 = sb + 1 == RC ? 0 : sb + 1;
           const int sb2 = sa2 + 1 == RC ? 0 : sa2 + 1;
           {
             const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qA);
-            qA = qt[(c + 2) * 64];
+            qA = qC;
+            qC = qt[(c + 4) * 64];
             my[sa * 64] = chunk_cells(chA, sc, 4 * c, hl, f, mkey, cp);
             chA = my[sa2 * 64];
           }
           {
             const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qB);
-            qB = qt[(c + 3) * 64];
+            qB = qD;
+            qD = qt[(c + 5) * 64];
             my[sb * 64] = chunk_cells(chB, sc, 4 * c + 4, hl, f, mkey, cp);
             chB = my[sb2 * 64];
           }
@@ -818,9 +871,11 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
             if (j < rend) {
               const uint32_t r = rec_get(ch, cc);
               constexpr uint32_t M = (1u << WB) - 1;
+              int key;
               rec_set(ch, cc,
                       cell<WB>(r & M, r >> WB, (int)(int8_t)(sc >> (8 * cc)), j, hl, f,
-                               mkey, cp));
+                               key, cp));
+              mkey = imax(mkey, key);
             }
           }
           my[sl * 64] = ch;
@@ -1025,8 +1080,9 @@ int lane8_ring_chunks(int cls, int wmax) {
   return need >= full ? full : (int)need;
 }
 
-// HBM words of query tile per workgroup of a chunked class
-size_t lane8_qtile_words(int cls) { return ((size_t)cls_cap(cls) / 4 + 3) * 64; }
+// HBM words of query tile per workgroup of a chunked class: the chunks of
+// the longest query plus the ones the loads run ahead by
+size_t lane8_qtile_words(int cls) { return ((size_t)cls_cap(cls) / 4 + 6) * 64; }
 
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s) {
   int64_t blocks = (nwords + 255) / 256;
