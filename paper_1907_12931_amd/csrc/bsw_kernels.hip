@@ -633,6 +633,70 @@ __device__ __forceinline__ uint4 chunk_cells(const uint4 ch, uint32_t sc, int j0
   mkey = imax3(imax3(mkey, k0, k1), k2, k3);
   return r;
 }
+// Packed 16-bit form of the four cells of an 8-bit chunk: the diagonal,
+// E and H terms of two columns at a time (v_pk_* on gfx950); only the F
+// recurrence along the row is sequential, and it is unrolled two columns
+// per step: F(j+1) = max(F(j) - e_ins, A(j)) with A(j) = max(M(j) - o_ins -
+// e_ins, 0), so F(j+2) = max(F(j) - 2 e_ins, A(j) - e_ins, A(j+1)).  Every
+// value fits 16 bits: stored values are bytes, scores are bytes, gap costs
+// are at most 2000.  The diagonal gate M = d ? d + s : 0 becomes
+// min(d + s, 128 d): for d >= 1 that is d + s, for d = 0 it is at most 0,
+// which gives the same H, E and F as M = 0 because E and F are >= 0.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ s16x2 pk(uint32_t x) { return __builtin_bit_cast(s16x2, x); }
+__device__ __forceinline__ uint32_t unpk(s16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ s16x2 pmax(s16x2 a, s16x2 b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ s16x2 pmin(s16x2 a, s16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ __forceinline__ s16x2 psubsat(s16x2 a, s16x2 b) {  // unsigned, floored at 0
+  return __builtin_bit_cast(
+      s16x2, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, a),
+                                           __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ s16x2 bcast(int v) { return (s16x2){(short)v, (short)v}; }
+
+struct PkParams {
+  s16x2 eD, oeD, oeI, eI, eI12;  // (e_del, e_del), ..., (e_ins, 2 e_ins)
+};
+
+// The four cells of an unmasked 8-bit chunk.  hl and f carry H(i, j0-1) and
+// F(i, j0) in and H(i, j0+3), F(i, j0+4) out; the chunk's largest H goes to
+// m4 (its column is found after the row from the stored values).
+template <bool SYM>
+__device__ __forceinline__ uint2 chunk_cells_pk(const uint2 ch, uint32_t sc, int& hl, int& f,
+                                                int& m4, const PkParams& pp) {
+  const s16x2 D01 = pk(__builtin_amdgcn_perm(0u, ch.x, 0x0c020c00u));
+  const s16x2 E01 = pk(__builtin_amdgcn_perm(0u, ch.x, 0x0c030c01u));
+  const s16x2 D23 = pk(__builtin_amdgcn_perm(0u, ch.y, 0x0c020c00u));
+  const s16x2 E23 = pk(__builtin_amdgcn_perm(0u, ch.y, 0x0c030c01u));
+  // scores, sign-extended in pairs: the sign of byte b is bit 15 of a word
+  // holding that byte at position 1
+  const uint32_t sc8 = sc << 8;
+  const s16x2 S01 = pk(__builtin_amdgcn_perm(sc8, sc, 0x08010a00u));
+  const s16x2 S23 = pk(__builtin_amdgcn_perm(sc8, sc, 0x09030b02u));
+  const s16x2 G01 = pmin(D01 + S01, D01 << 7), G23 = pmin(D23 + S23, D23 << 7);
+  const s16x2 TD01 = G01 - pp.oeD, TD23 = G23 - pp.oeD;
+  const s16x2 EN01 = pmax(psubsat(E01, pp.eD), TD01);
+  const s16x2 EN23 = pmax(psubsat(E23, pp.eD), TD23);
+  const s16x2 z = bcast(0);
+  const s16x2 A01 = pmax(SYM ? TD01 : G01 - pp.oeI, z);
+  const s16x2 A23 = pmax(SYM ? TD23 : G23 - pp.oeI, z);
+  const s16x2 F12 = pmax(pmax(A01, bcast(A01[0]) - pp.eI), bcast(f) - pp.eI12);
+  const s16x2 F34 = pmax(pmax(A23, bcast(A23[0]) - pp.eI), bcast(F12[1]) - pp.eI12);
+  const s16x2 F01 = (s16x2){(short)f, F12[0]}, F23 = (s16x2){F12[1], F34[0]};
+  const s16x2 H01 = pmax(pmax(G01, E01), F01), H23 = pmax(pmax(G23, E23), F23);
+  // records (H(i, j-1), E(i+1, j)): x = (hl, en0, h0, en1), y = (h1, en2, h2, en3)
+  const uint32_t hx = __builtin_amdgcn_perm(unpk(H01), (uint32_t)hl, 0x05040100u);
+  const uint32_t x = __builtin_amdgcn_perm(unpk(EN01), hx, 0x06020400u);
+  const uint32_t hy = __builtin_amdgcn_perm(unpk(H23), unpk(H01), 0x0c040c02u);
+  const uint32_t y = __builtin_amdgcn_perm(unpk(EN23), hy, 0x06020400u);
+  const s16x2 m2 = pmax(H01, H23);
+  m4 = imax(m2[0], m2[1]);
+  hl = H23[1];
+  f = F34[1];
+  return make_uint2(x, y);
+}
+
 // column cc of a chunk, read and written as a record
 __device__ __forceinline__ uint32_t rec_get(const uint2& c, int cc) {
   return ((cc < 2 ? c.x : c.y) >> (16 * (cc & 1))) & 0xffffu;
@@ -721,6 +785,8 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
     const int Lq = pd.ql, Lt = valid ? pd.tl : 0, h0 = pd.h0;
     const int oD = P.o_del, eD = P.e_del, oI = P.o_ins, eI = P.e_ins;
     const CellParams cp = {eD, P.oe_del, eI, SYM ? P.oe_del : P.oe_ins};
+    const PkParams pp = {bcast(eD), bcast(P.oe_del), bcast(SYM ? P.oe_del : P.oe_ins),
+                         bcast(eI), (s16x2){(short)eI, (short)(2 * eI)}};
     const int zd = P.zdrop;
     const int wb = band_cap(P, Lq);
     uint32_t pl[5], ph[5];
@@ -821,6 +887,9 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
       const int cf = wave_min(live ? (rend >> 2) : 0x7fffffff);
       const int c1 = wave_max(live ? ((rend + 3) >> 2) : 0);
       int mkey = 0;
+      // 8-bit unmasked chunks keep the row maximum per chunk: the largest
+      // chunk maximum and the last chunk that reached it
+      int mrun = -1, mch = 0;
       int c = c0;
       if (c < cf) {
         // two chunks per step, A = chunk c and B = chunk c+1; each load is
@@ -840,14 +909,28 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
             const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qA);
             qA = qC;
             qC = qt[(c + 4) * 64];
-            my[sa * 64] = chunk_cells(chA, sc, 4 * c, hl, f, mkey, cp);
+            if constexpr (WB == 8) {
+              int m4;
+              my[sa * 64] = chunk_cells_pk<SYM>(chA, sc, hl, f, m4, pp);
+              mch = m4 >= mrun ? c : mch;
+              mrun = imax(mrun, m4);
+            } else {
+              my[sa * 64] = chunk_cells(chA, sc, 4 * c, hl, f, mkey, cp);
+            }
             chA = my[sa2 * 64];
           }
           {
             const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qB);
             qB = qD;
             qD = qt[(c + 5) * 64];
-            my[sb * 64] = chunk_cells(chB, sc, 4 * c + 4, hl, f, mkey, cp);
+            if constexpr (WB == 8) {
+              int m4;
+              my[sb * 64] = chunk_cells_pk<SYM>(chB, sc, hl, f, m4, pp);
+              mch = m4 >= mrun ? c + 1 : mch;
+              mrun = imax(mrun, m4);
+            } else {
+              my[sb * 64] = chunk_cells(chB, sc, 4 * c + 4, hl, f, mkey, cp);
+            }
             chB = my[sb2 * 64];
           }
           sa = sa2;
@@ -855,7 +938,14 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         }
         if (c < cf) {
           const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qA);
-          my[sa * 64] = chunk_cells(chA, sc, 4 * c, hl, f, mkey, cp);
+          if constexpr (WB == 8) {
+            int m4;
+            my[sa * 64] = chunk_cells_pk<SYM>(chA, sc, hl, f, m4, pp);
+            mch = m4 >= mrun ? c : mch;
+            mrun = imax(mrun, m4);
+          } else {
+            my[sa * 64] = chunk_cells(chA, sc, 4 * c, hl, f, mkey, cp);
+          }
           ++c;
         }
       }
@@ -889,7 +979,17 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
           gi = hl >= gbest ? i : gi;
           gbest = imax(gbest, hl);
         }
-        const int m = mkey >> 9, mj = mkey & 511;
+        // row maximum (ties to the larger column): the masked chunks lie
+        // right of the unmasked ones, so they win ties; an unmasked chunk's
+        // column is the last of its four cells holding the maximum, whose
+        // H(i, j) now sit at columns j + 1
+        int m = mkey >> 9, mj = mkey & 511;
+        if (WB == 8 && mrun > m) {
+          m = mrun;
+          const int j0 = 4 * mch;
+          mj = j0 + 3;
+          while (mj > j0 && (int)(COL(mj + 1) & 0xff) != m) --mj;
+        }
         if (m == 0) {
           stop = 1;
           live = false;
