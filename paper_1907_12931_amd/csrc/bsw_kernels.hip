@@ -697,6 +697,28 @@ __device__ __forceinline__ uint2 chunk_cells_pk(const uint2 ch, uint32_t sc, int
   return make_uint2(x, y);
 }
 
+// The low `bits` bits of a dword (0..32): ~(~0 << bits) taken from a 64-bit
+// shift, so that bits = 32 gives all ones.
+__device__ __forceinline__ uint32_t low_bits(int bits) { return ~(uint32_t)(~0ull << bits); }
+
+// The same for a chunk that holds the band end of some lane (k = end - j0
+// for this lane).  Columns at or past end read as zero, so M <= 0 there and
+// their H is below H(i, end-1) (or zero): the chunk maximum is unchanged.
+// They keep their stored values, except that column end takes H(i, end-1)
+// in its H byte (the right edge of the band, R8) and keeps its E (zero).
+template <bool SYM>
+__device__ __forceinline__ uint2 chunk_cells_pk_masked(const uint2 ch, uint32_t sc, int k,
+                                                       int& hl, int& f, int& m4,
+                                                       const PkParams& pp) {
+  const int n = imin(imax(k, 0), 4);             // columns read
+  const int nb = imin(imax(2 * k + 1, 0), 8);    // bytes written
+  const uint2 in = make_uint2(ch.x & low_bits(16 * imin(n, 2)),
+                              ch.y & low_bits(16 * imax(n - 2, 0)));
+  const uint2 r = chunk_cells_pk<SYM>(in, sc, hl, f, m4, pp);
+  const uint32_t mx = low_bits(8 * imin(nb, 4)), my = low_bits(8 * imax(nb - 4, 0));
+  return make_uint2((r.x & mx) | (ch.x & ~mx), (r.y & my) | (ch.y & ~my));
+}
+
 // column cc of a chunk, read and written as a record
 __device__ __forceinline__ uint32_t rec_get(const uint2& c, int cc) {
   return ((cc < 2 ? c.x : c.y) >> (16 * (cc & 1))) & 0xffffu;
@@ -949,6 +971,16 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
           ++c;
         }
       }
+      if constexpr (WB == 8) {
+        for (; c < c1; ++c) {
+          const int sl = ring_slot(c, RC);
+          const uint32_t sc = __builtin_amdgcn_perm(hi, lo, qt[c * 64]);
+          int m4;
+          my[sl * 64] = chunk_cells_pk_masked<SYM>(my[sl * 64], sc, rend - 4 * c, hl, f, m4, pp);
+          mch = m4 >= mrun ? c : mch;
+          mrun = imax(mrun, m4);
+        }
+      }
       for (; c < c1; ++c) {
         const int j0 = 4 * c;
         if (j0 < rend) {
@@ -972,22 +1004,26 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         }
       }
       if (live) {
-        // right edge (R8): H(i, end-1) at index end; E there is already 0
-        COL(end) = (R)(hl & CK::MAXV);
+        // right edge (R8): H(i, end-1) at index end; E there is already 0.
+        // With 8-bit records the masked chunk holding column end wrote it;
+        // when end is a chunk boundary no chunk held it, and the last chunk
+        // was fully inside the band, so hl is H(i, end-1)
+        if (WB != 8 || end == 4 * c1) COL(end) = (R)(hl & CK::MAXV);
         // best score touching the end of the query (Sec. 5.4 (b))
         if (imax(beg, end) == Lq) {
-          gi = hl >= gbest ? i : gi;
-          gbest = imax(gbest, hl);
+          const int hend = WB == 8 ? (int)(COL(end) & 0xff) : hl;
+          gi = hend >= gbest ? i : gi;
+          gbest = imax(gbest, hend);
         }
-        // row maximum (ties to the larger column): the masked chunks lie
-        // right of the unmasked ones, so they win ties; an unmasked chunk's
-        // column is the last of its four cells holding the maximum, whose
-        // H(i, j) now sit at columns j + 1
+        // row maximum (ties to the larger column): for 8-bit records the
+        // chunks keep the largest chunk maximum and the last chunk that
+        // reached it; the column is the last of that chunk's cells inside
+        // the band holding the maximum, whose H(i, j) now sit at j + 1
         int m = mkey >> 9, mj = mkey & 511;
-        if (WB == 8 && mrun > m) {
-          m = mrun;
+        if (WB == 8) {
+          m = imax(mrun, 0);  // no chunk at all: an empty band
           const int j0 = 4 * mch;
-          mj = j0 + 3;
+          mj = imin(j0 + 3, end - 1);
           while (mj > j0 && (int)(COL(mj + 1) & 0xff) != m) --mj;
         }
         if (m == 0) {
