@@ -82,10 +82,8 @@ def kernel_symbol(cls, scorings):
                         for x in scorings) else "false"
     if cls == "long":
         return "bsw::k_long"
-    if cls == "rerun16":
-        return f"bsw::k_lanec<256, {sym}, 16>"
-    if cls == "rerun32":
-        return "bsw::k_lane<2, 256, true>"
+    if cls == "rerun":
+        return "bsw::k_wave"
     width, cap = cls[4:].split("_q")
     if width == "32":
         return f"bsw::k_lane<2, {cap}, true>"

@@ -192,7 +192,8 @@ int bsw_ctx_last_kernels(bsw_ctx* ctx, int32_t* cls, int64_t* cells, double* ms,
                          int32_t max);
 
 /* Name of a kernel class ("lane8_q256" = one pair per lane, 8-bit row
- * buffer, queries up to 256; "rerun16" = 16-bit rerun of 8-bit overflows). */
+ * buffer, queries up to 256; "rerun" = one pair per wave with 32-bit values,
+ * for the pairs a class could not settle in its record width). */
 const char* bsw_class_name(int32_t cls);
 
 /* ------------------------------------------------------------------------

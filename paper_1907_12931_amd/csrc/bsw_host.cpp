@@ -47,6 +47,11 @@ void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
                  uint32_t* tile_ctr, const Status* st, uint32_t* qtiles,
                  PairDesc* ovf, long long* ovf_count, int ring, bool sym,
                  unsigned long long* cls_cells, hipStream_t s);
+void launch_wave(unsigned blocks, const PairDesc* desc, const long long* range,
+                 const uint8_t* q, const uint8_t* t, const KParams* kp, bsw_result* out,
+                 bsw_diag* diag, uint32_t* ctr, const Status* st,
+                 unsigned long long* cls_cells, hipStream_t s);
+int wave_blocks_per_cu();
 void launch_long(const PairDesc* desc, const long long* range, const uint8_t* q,
                  const uint8_t* t, const KParams* kp, bsw_result* out,
                  bsw_diag* diag, uint32_t* ctr, int2* gbuf, uint8_t* gq,
@@ -118,11 +123,11 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up for n pairs.
 struct Layout {
-  size_t keys, desc, ovf, ovf2, hist, cursor, cls_range, status, ctr, zero_beg, zero_end,
+  size_t keys, desc, ovf, hist, cursor, cls_range, status, ctr, zero_beg, zero_end,
       total;
 };
 
-constexpr int NCTR = NCLS + 3;  // one tile counter per class, two reruns, spare
+constexpr int NCTR = NCLS + 2;  // one tile counter per class, the rerun, spare
 
 Layout layout_for(int64_t n) {
   Layout L;
@@ -145,8 +150,6 @@ Layout layout_for(int64_t n) {
   L.desc = o;
   o = align_up(o + (size_t)n * sizeof(PairDesc), 256);
   L.ovf = o;
-  o = align_up(o + (size_t)n * sizeof(PairDesc), 256);
-  L.ovf2 = o;
   o = align_up(o + (size_t)n * sizeof(PairDesc), 256);
   L.total = o;
   return L;
@@ -259,6 +262,7 @@ struct bsw_ctx {
   Status* h_status = nullptr;  // pinned
   long long* h_cls = nullptr;  // pinned [NCLS][2]
   int blocks_per_cu[2][NCLS] = {};
+  int wave_per_cu = 1;  // resident groups per CU of the rerun kernel
   // occupancy of the chunked classes by (symmetric variant, ring chunks)
   int occc[2][NCLS][80] = {};
   bool pending = false;
@@ -293,7 +297,6 @@ struct Work {
   uint32_t* cursor;
   long long* cls_range;
   PairDesc* ovf;
-  PairDesc* ovf2;
   uint32_t* keys;
   PairDesc* desc;
   uint32_t* zero;
@@ -308,7 +311,6 @@ Work carve(char* base, const Layout& L) {
   w.cursor = (uint32_t*)(base + L.cursor);
   w.cls_range = (long long*)(base + L.cls_range);
   w.ovf = (PairDesc*)(base + L.ovf);
-  w.ovf2 = (PairDesc*)(base + L.ovf2);
   w.keys = (uint32_t*)(base + L.keys);
   w.desc = (PairDesc*)(base + L.desc);
   w.zero = (uint32_t*)(base + L.zero_beg);
@@ -372,17 +374,14 @@ int tuned_per_cu(const bsw_ctx* c, int cls, int fit) {
   return t < 1 ? 1 : t;
 }
 
-constexpr int R1CLS = CLS_W16 + NLW - 1;  // chunked 16-bit rerun of 8-bit overflows
-constexpr int R2CLS = CLS_W32 + NLW - 1;  // 32-bit rerun of 16-bit overflows
-
 // Launch shapes of the batched path.  They depend only on the band limit,
 // the gap symmetry and the device, never on the data: every class gets a
 // full persistent grid that drains its list from a device-side counter and
 // exits at once when the list is empty.
 struct BatchedPlan {
-  int64_t blocks[NCLS + 2] = {};  // per class, then the two reruns
-  int ring[NCLS + 2] = {};
-  size_t qt_off[NCLS + 2] = {};
+  int64_t blocks[NCLS + 1] = {};  // per class, then the rerun
+  int ring[NCLS + 1] = {};
+  size_t qt_off[NCLS + 1] = {};
   size_t qt_words = 0;
 };
 
@@ -400,11 +399,7 @@ BatchedPlan plan_batched(bsw_ctx* c, int wmax, bool sym) {
       p.qt_words += (size_t)p.blocks[cls] * lane8_qtile_words(cls);
     }
   }
-  p.ring[NCLS] = lane8_ring_chunks(R1CLS, wmax);
-  p.blocks[NCLS] = (int64_t)chunked_per_cu(c, R1CLS, sym, p.ring[NCLS]) * c->num_cu;
-  p.qt_off[NCLS] = p.qt_words;
-  p.qt_words += (size_t)p.blocks[NCLS] * lane8_qtile_words(R1CLS);
-  p.blocks[NCLS + 1] = (int64_t)c->blocks_per_cu[1][R2CLS] * c->num_cu;
+  p.blocks[NCLS] = (int64_t)c->wave_per_cu * c->num_cu;
   return p;
 }
 
@@ -436,12 +431,12 @@ int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan&
     const int cls = order[oi];
     hipStream_t ls = c->side[oi % nside];
     if ((rc = begin_launch(c, cls, ls))) return rc;
-    // 8-bit overflows go to the first rerun list, 16-bit ones to the second
+    // pairs a chunked class cannot settle in its record width go to the
+    // rerun list
     launch_lane(cls, true, (unsigned)p.blocks[cls], w.desc, w.cls_range + 2 * cls, a.q,
                 a.t, c->d_kp, a.out, a.diag, w.ctr + cls, st,
-                cls < CLS_W32 ? qt + p.qt_off[cls] : nullptr, cls < CLS_W16 ? w.ovf : w.ovf2,
-                cls < CLS_W16 ? &st->ovf_range[1] : &st->ovf2_range[1], p.ring[cls], sym,
-                &st->cls_cells[cls], ls);
+                cls < CLS_W32 ? qt + p.qt_off[cls] : nullptr, w.ovf, &st->ovf_range[1],
+                p.ring[cls], sym, &st->cls_cells[cls], ls);
     if ((rc = end_launch(c, ls))) return rc;
   }
   for (int k = 0; k < nside; ++k) {
@@ -452,15 +447,10 @@ int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan&
   launch_long(w.desc, w.cls_range + 2 * CLS_LONG, a.q, a.t, c->d_kp, a.out, a.diag,
               w.ctr + CLS_LONG, gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
   if ((rc = end_launch(c, s))) return rc;
+  // the rerun, one pair per wave with 32-bit values
   if ((rc = begin_launch(c, NCLS, s))) return rc;
-  launch_lane(R1CLS, true, (unsigned)p.blocks[NCLS], w.ovf, st->ovf_range, a.q, a.t,
-              c->d_kp, a.out, a.diag, w.ctr + NCLS, st, qt + p.qt_off[NCLS], w.ovf2,
-              &st->ovf2_range[1], p.ring[NCLS], sym, &st->cls_cells[NCLS], s);
-  if ((rc = end_launch(c, s))) return rc;
-  if ((rc = begin_launch(c, NCLS + 1, s))) return rc;
-  launch_lane(R2CLS, true, (unsigned)p.blocks[NCLS + 1], w.ovf2, st->ovf2_range, a.q, a.t,
-              c->d_kp, a.out, a.diag, w.ctr + NCLS + 1, st, nullptr, nullptr, nullptr, 0,
-              false, &st->cls_cells[NCLS + 1], s);
+  launch_wave((unsigned)p.blocks[NCLS], w.ovf, st->ovf_range, a.q, a.t, c->d_kp, a.out,
+              a.diag, w.ctr + NCLS, st, &st->cls_cells[NCLS], s);
   if ((rc = end_launch(c, s))) return rc;
   HIPCHK(hipGetLastError());
   if (ev) HIPCHK(hipEventRecord(c->ev[3], s));
@@ -646,10 +636,6 @@ int run_plain(bsw_ctx* c, const Args& a, hipStream_t s) {
       qt_words += (size_t)blocks[cls] * lane8_qtile_words(cls);
     }
   }
-  const int r1ring = lane8_ring_chunks(R1CLS, wmax);
-  const int64_t r1blocks = any8 ? (int64_t)chunked_per_cu(c, R1CLS, sym, r1ring) * c->num_cu : 0;
-  const size_t r1qt = qt_words;
-  qt_words += (size_t)r1blocks * lane8_qtile_words(R1CLS);
   if (qt_words && (rc = c->qtiles.ensure(qt_words * 4))) return rc;
   uint32_t* qt = (uint32_t*)c->qtiles.p;
   c->n_launch = 0;
@@ -663,9 +649,7 @@ int run_plain(bsw_ctx* c, const Args& a, hipStream_t s) {
     if ((rc = begin_launch(c, cls, s))) return rc;
     launch_lane(cls, false, (unsigned)blocks[cls], w.desc, w.cls_range + 2 * cls, a.q, a.t,
                 c->d_kp, a.out, a.diag, w.ctr + cls, st, qt ? qt + qt_off[cls] : nullptr,
-                cls < CLS_W16 ? w.ovf : w.ovf2,
-                cls < CLS_W16 ? &st->ovf_range[1] : &st->ovf2_range[1], ring[cls], sym,
-                &st->cls_cells[cls], s);
+                w.ovf, &st->ovf_range[1], ring[cls], sym, &st->cls_cells[cls], s);
     if ((rc = end_launch(c, s))) return rc;
   }
   if (c->h_cls[2 * CLS_LONG + 1] > 0) {
@@ -678,20 +662,12 @@ int run_plain(bsw_ctx* c, const Args& a, hipStream_t s) {
                 w.ctr + CLS_LONG, gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
     if ((rc = end_launch(c, s))) return rc;
   }
-  // reruns: their counts are only known on the device, so the grids are
-  // persistent and exit at once when their list is empty
-  if (any8) {
-    if ((rc = begin_launch(c, NCLS, s))) return rc;
-    launch_lane(R1CLS, true, (unsigned)r1blocks, w.ovf, st->ovf_range, a.q, a.t, c->d_kp,
-                a.out, a.diag, w.ctr + NCLS, st, qt + r1qt, w.ovf2, &st->ovf2_range[1],
-                r1ring, sym, &st->cls_cells[NCLS], s);
-    if ((rc = end_launch(c, s))) return rc;
-  }
+  // the rerun: its count is only known on the device, so the grid is
+  // persistent and exits at once when the list is empty
   if (any8 || any16) {
-    if ((rc = begin_launch(c, NCLS + 1, s))) return rc;
-    launch_lane(R2CLS, true, (unsigned)(c->blocks_per_cu[1][R2CLS] * c->num_cu), w.ovf2,
-                st->ovf2_range, a.q, a.t, c->d_kp, a.out, a.diag, w.ctr + NCLS + 1, st,
-                nullptr, nullptr, nullptr, 0, false, &st->cls_cells[NCLS + 1], s);
+    if ((rc = begin_launch(c, NCLS, s))) return rc;
+    launch_wave((unsigned)(c->wave_per_cu * c->num_cu), w.ovf, st->ovf_range, a.q, a.t,
+                c->d_kp, a.out, a.diag, w.ctr + NCLS, st, &st->cls_cells[NCLS], s);
     if ((rc = end_launch(c, s))) return rc;
   }
   HIPCHK(hipGetLastError());
@@ -796,7 +772,7 @@ int ctx_finish(bsw_ctx* c) { return finish_call(c); }
 
 unsigned long long ctx_last_cells(const bsw_ctx* c) {
   unsigned long long sum = 0;
-  for (int k = 0; k < NCLS + 2; ++k) sum += c->h_status->cls_cells[k];
+  for (int k = 0; k <= NCLS; ++k) sum += c->h_status->cls_cells[k];
   return sum;
 }
 
@@ -869,6 +845,7 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
       (void)lane_setup(cls, p == 1);
       c->blocks_per_cu[p][cls] = lane_blocks_per_cu(cls, p == 1, 0);
     }
+  c->wave_per_cu = wave_blocks_per_cu();
   (void)hipGetLastError();
   if (rc != BSW_OK) {
     bsw_ctx_destroy(c);
@@ -1027,12 +1004,12 @@ int bsw_ctx_last_kernels(bsw_ctx* c, int32_t* cls, int64_t* cells, double* ms,
 }
 
 const char* bsw_class_name(int32_t cls) {
-  static const char* names[NCLS + 2] = {
+  static const char* names[NCLS + 1] = {
       "lane8_q32",  "lane8_q64",  "lane8_q96",  "lane8_q128", "lane8_q160",
       "lane8_q192", "lane8_q224", "lane8_q256", "lane16_q32", "lane16_q64",
       "lane16_q128", "lane16_q256", "lane32_q32", "lane32_q64", "lane32_q128",
-      "lane32_q256", "long", "rerun16", "rerun32"};
-  return cls >= 0 && cls <= NCLS + 1 ? names[cls] : "?";
+      "lane32_q256", "long", "rerun"};
+  return cls >= 0 && cls <= NCLS ? names[cls] : "?";
 }
 
 int bsw_ctx_last_timing(bsw_ctx* c, double out4[4]) {

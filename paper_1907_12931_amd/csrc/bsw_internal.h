@@ -62,8 +62,7 @@ struct Status {
   uint32_t pad_;
   unsigned long long first_bad_inv;  // ~(smallest bad pair index); 0 = none
   unsigned long long long_max;   // largest query length in the long class
-  long long ovf_range[2];        // {0, number of 8-bit overflow reruns}
-  long long ovf2_range[2];       // {0, number of 16-bit overflow reruns}
+  long long ovf_range[2];        // {0, number of pairs queued for the rerun}
   unsigned long long cls_cells[32];  // band cells per class (+ rerun slot)
 };
 

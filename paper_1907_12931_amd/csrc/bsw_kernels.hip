@@ -1086,6 +1086,168 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
 #undef COL
 }
 
+// One pair per wave (the reruns of pairs whose values need more than their
+// class's record width): the 64 lanes take 64 consecutive columns of a row
+// at a time, with 32-bit values, so a pair's rows take a few wave steps
+// each instead of one lane's sequential walk.  Along the row only F is
+// sequential; unrolled over a block of columns it is a max-plus prefix:
+// F(jb + l) = max(0, F(jb) - l e, max over l' < l of (M(jb + l') - o - e +
+// l' e) - (l - 1) e) with the insertion costs o, e, taken with a wave scan.
+// The row buffer (H shifted by one column, and E, Sec. 5.1) holds every
+// column of the query in LDS and is never reset, as in the one-lane form.
+constexpr int WAVE_CAP = 256;  // longest query of the wave kernel
+constexpr int NEG = -(1 << 30);
+
+__device__ __forceinline__ int wave_prefix_max_excl(int x) {
+  const int lane = threadIdx.x & 63;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x = x > y ? x : y;
+  }
+  const int e = __shfl_up(x, 1, 64);
+  return lane ? e : NEG;
+}
+
+__global__ void __launch_bounds__(64)
+k_wave(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
+       const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
+       const KParams* __restrict__ kp, bsw_result* __restrict__ out,
+       bsw_diag* __restrict__ diag, uint32_t* ctr, const Status* st,
+       unsigned long long* __restrict__ cls_cells) {
+  if (st->bad) return;
+  __shared__ int2 hb[WAVE_CAP + 1];
+  const int lane = threadIdx.x;
+  const long long begin = range[0], count = range[1];
+  unsigned long long acc = 0;
+  for (;;) {
+    uint32_t v0 = 0;
+    if (lane == 0) v0 = atomicAdd(ctr, 1u);
+    const uint32_t k = wave_first(__shfl(v0, 0));
+    if (k >= count) break;
+    const PairDesc pd = desc[begin + k];
+    const KParams& P = kp[pd.pid];
+    const int Lq = pd.ql, Lt = pd.tl, h0 = pd.h0;
+    const int oD = P.o_del, eD = P.e_del, oI = P.o_ins, eI = P.e_ins;
+    const int oeD = P.oe_del, oeI = P.oe_ins, zd = P.zdrop;
+    const int wb = band_cap(P, Lq);
+    const uint8_t* qs = q + pd.qo;
+    const uint8_t* ts = t + pd.to;
+    // first row of Eq. (3)
+    for (int j = lane; j <= Lq; j += 64)
+      hb[j] = make_int2(j == 0 ? h0 : imax(0, h0 - oI - eI * j), 0);
+    __syncthreads();
+    int best = h0, bi = -1, bj = -1, gbest = -1, gi = -1, moff = 0;
+    int beg = 0, end = Lq, rows = 0, stop = 0;
+    long long cells = 0;
+    for (int i = 0; i < Lt; ++i) {
+      ++rows;
+      beg = imax(beg, i - wb);
+      end = imin(imin(end, i + wb + 1), Lq);
+      if (end > beg) cells += end - beg;
+      const int tb = ts[i];
+      uint32_t lo = P.prow[0][0], hi = P.prow[0][1];
+#pragma unroll
+      for (int a = 1; a < 5; ++a) {
+        lo = tb == a ? P.prow[a][0] : lo;
+        hi = tb == a ? P.prow[a][1] : hi;
+      }
+      int hl = beg == 0 ? imax(0, h0 - oD - eD * (i + 1)) : 0;  // H(i, jb - 1)
+      int fin = 0;                                                 // F(i, jb)
+      int m = 0, mj = -1;
+      for (int jb = beg; jb < end; jb += 64) {
+        const int j = jb + lane;
+        const bool in = j < end;
+        const int2 r = in ? hb[j] : make_int2(0, 0);
+        const int s = in ? score_of(lo, hi, qs[j]) : 0;
+        const int M = r.x > 0 ? r.x + s : 0;
+        const int en = imax(imax(r.y - eD, M - oeD), 0);
+        const int X = wave_prefix_max_excl(in ? M - oeI + lane * eI : NEG);
+        const int F = imax(imax(fin - lane * eI, X - (lane - 1) * eI), 0);
+        const int h = imax(imax(M, r.y), F);
+        const int Fn = imax(imax(F - eI, M - oeI), 0);
+        const int hprev = __shfl_up(h, 1, 64);
+        if (in) hb[j] = make_int2(lane ? hprev : hl, en);
+        const int hv = in ? h : -1;
+        const int bm = wave_max(hv);
+        if (bm >= m) {
+          m = bm;
+          mj = jb + 63 - __builtin_clzll(__ballot(hv == bm));
+        }
+        const int last = imin(63, end - 1 - jb);
+        hl = __builtin_amdgcn_readlane(h, last);
+        fin = __builtin_amdgcn_readlane(Fn, last);
+      }
+      // right edge (R8): H(i, end-1), E = 0 at index end
+      if (lane == 0) hb[end] = make_int2(hl, 0);
+      __syncthreads();
+      if (imax(beg, end) == Lq) {
+        gi = hl >= gbest ? i : gi;
+        gbest = imax(gbest, hl);
+      }
+      if (m == 0) {
+        stop = 1;
+        break;
+      }
+      if (m > best) {
+        best = m;
+        bi = i;
+        bj = mj;
+        moff = imax(moff, mj > i ? mj - i : i - mj);
+      } else if (zd > 0) {
+        const int drift = (i - bi) - (mj - bj);
+        const int drop = best - m - (drift > 0 ? drift * eD : -drift * eI);
+        if (drop > zd) {
+          stop = 2;
+          break;
+        }
+      }
+      // shrink the band by its empty ends (Sec. 5.1 (c))
+      int nb = end;
+      for (int jb = beg; jb < end; jb += 64) {
+        const int j = jb + lane;
+        const unsigned long long mk =
+            __ballot(j < end && (hb[j].x != 0 || hb[j].y != 0));
+        if (mk) {
+          nb = jb + __builtin_ctzll(mk);
+          break;
+        }
+      }
+      beg = nb;
+      int x = beg - 1;
+      for (int jt = end; jt >= beg; jt -= 64) {
+        const int j = jt - lane;
+        const unsigned long long mk =
+            __ballot(j >= beg && (hb[j].x != 0 || hb[j].y != 0));
+        if (mk) {
+          x = jt - __builtin_ctzll(mk);
+          break;
+        }
+      }
+      end = imin(x + 2, Lq);
+    }
+    if (lane == 0) {
+      bsw_result res;
+      res.score = best;
+      res.qle = bj + 1;
+      res.tle = bi + 1;
+      res.gtle = gi + 1;
+      res.gscore = gbest;
+      res.max_off = moff;
+      out[pd.idx] = res;
+      if (diag) {
+        bsw_diag dg;
+        dg.rows = rows;
+        dg.stop = stop;
+        dg.cells = cells;
+        diag[pd.idx] = dg;
+      }
+      acc += (unsigned long long)cells;
+    }
+    __syncthreads();  // the next pair rewrites the row buffer
+  }
+  if (lane == 0 && acc) atomicAdd(cls_cells, acc);
+}
+
 // Queries longer than 256: one pair per wave, lane 0 runs it with a
 // 32-bit row buffer in HBM (slot per wave); waves pull pairs from a counter.
 __global__ void __launch_bounds__(64)
@@ -1284,6 +1446,20 @@ void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
     hipLaunchKernelGGL(lanew_fn(cls, persist), dim3(blocks), dim3(wpb * 64),
                        lane_lds_per_wave(cls) * wpb, s, desc, range, q, t, kp, out, diag,
                        tile_ctr, st, cls_cells);
+}
+
+void launch_wave(unsigned blocks, const PairDesc* desc, const long long* range,
+                 const uint8_t* q, const uint8_t* t, const KParams* kp, bsw_result* out,
+                 bsw_diag* diag, uint32_t* ctr, const Status* st,
+                 unsigned long long* cls_cells, hipStream_t s) {
+  hipLaunchKernelGGL(k_wave, dim3(blocks), dim3(64), 0, s, desc, range, q, t, kp, out, diag,
+                     ctr, st, cls_cells);
+}
+
+int wave_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave, 64, 0) != hipSuccess) return 1;
+  return nb < 1 ? 1 : nb;
 }
 
 void launch_long(const PairDesc* desc, const long long* range, const uint8_t* q,
