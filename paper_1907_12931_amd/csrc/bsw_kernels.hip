@@ -97,23 +97,24 @@ __global__ void k_fill(uint32_t* p, int64_t nwords) {
 }
 
 // Wave-wide inclusive prefix sum and prefix maximum (lane l gets the
-// result over lanes 0..l).  Every lane must be active.
-__device__ __forceinline__ int wave_prefix_sum(int x) {
-  const int lane = threadIdx.x & 63;
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
+// result over lanes 0..l), with DPP: shifts by 1, 2, 4 and 8 lanes inside
+// each row of 16 (lanes without a source take the identity), then the last
+// lane of row 0 and of row 2 is broadcast into rows 1 and 3, and lane 31
+// into rows 2 and 3.  Every lane must be active.
+template <bool MAX>
+__device__ __forceinline__ int wave_scan(int x) {
+  constexpr int ID = MAX ? -(1 << 30) : 0;
+  auto op = [](int a, int b) { return MAX ? (a > b ? a : b) : a + b; };
+  x = op(x, __builtin_amdgcn_update_dpp(ID, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+  x = op(x, __builtin_amdgcn_update_dpp(ID, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+  x = op(x, __builtin_amdgcn_update_dpp(ID, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+  x = op(x, __builtin_amdgcn_update_dpp(ID, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+  x = op(x, __builtin_amdgcn_update_dpp(ID, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  x = op(x, __builtin_amdgcn_update_dpp(ID, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
   return x;
 }
-__device__ __forceinline__ int wave_prefix_max(int x) {
-  const int lane = threadIdx.x & 63;
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(x, d, 64);
-    if (lane >= d) x = x > y ? x : y;
-  }
-  return x;
-}
+__device__ __forceinline__ int wave_prefix_sum(int x) { return wave_scan<false>(x); }
+__device__ __forceinline__ int wave_prefix_max(int x) { return wave_scan<true>(x); }
 
 // Estimated rows of a pair for the sort key: walk the main diagonal without
 // gaps from h0 until the running score falls to zero or more than z-drop
@@ -223,8 +224,8 @@ k_prep(int64_t n, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
     int tq = rows_est >> 4;
     qq = qq > 63 ? 63 : qq;
     tq = tq > 63 ? 63 : (tq < 0 ? 0 : tq);
-    const uint32_t key = ((uint32_t)cls << KEY_SUB_BITS) |
-                         ((uint32_t)(63 - qq) << 6) | (uint32_t)(63 - tq);
+    const uint32_t sub = ((uint32_t)(63 - qq) << 6) | (uint32_t)(63 - tq);
+    const uint32_t key = ((uint32_t)cls << KEY_SUB_BITS) | sub;
     keys[k] = key;
     atomicAdd(&hist[key], 1u);
   }
@@ -1099,13 +1100,8 @@ constexpr int WAVE_CAP = 256;  // longest query of the wave kernel
 constexpr int NEG = -(1 << 30);
 
 __device__ __forceinline__ int wave_prefix_max_excl(int x) {
-  const int lane = threadIdx.x & 63;
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(x, d, 64);
-    if (lane >= d) x = x > y ? x : y;
-  }
-  const int e = __shfl_up(x, 1, 64);
-  return lane ? e : NEG;
+  // shift the inclusive scan one lane up across the whole wave
+  return __builtin_amdgcn_update_dpp(NEG, wave_scan<true>(x), 0x138, 0xf, 0xf, false);
 }
 
 __global__ void __launch_bounds__(64)
