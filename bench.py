@@ -114,7 +114,7 @@ def serve(bsw, synth, batch, host, capacity, rho, n_requests, seed=3):
             for a, m in zip(starts.tolist(), sizes.tolist())]
     tickets = [None] * n_requests
     ready = threading.Semaphore(0)
-    with bsw.Server(batch["scorings"], max_inflight=2, hbm_budget=8 << 30) as srv:
+    with bsw.Server(batch["scorings"], hbm_budget=8 << 30) as srv:
         def waiter():
             for k in range(n_requests):
                 ready.acquire()

@@ -290,7 +290,7 @@ class Server:
     from host memory, admitted in arrival order under the device budget and
     run in batches formed from every resident request when a slot frees."""
 
-    def __init__(self, scorings, device=0, max_inflight=2, max_batch_pairs=0,
+    def __init__(self, scorings, device=0, max_inflight=0, max_batch_pairs=0,
                  hbm_budget=0, max_queued=0, min_lane_bits=0):
         o = ServerOpts(device, max_inflight, max_batch_pairs, hbm_budget, max_queued,
                        min_lane_bits)

@@ -345,8 +345,8 @@ void enqueue_prep_bin(bsw_ctx* c, const Args& a, const Work& w, hipStream_t s) {
   launch_prep(a.n, a.q, a.t, a.q_off, qe, a.t_off, te, a.h0, a.pid, a.n_params, c->d_kp,
               c->opts.min_lane_bits, c->tune.spec16, w.keys, w.hist, w.st, s);
   if (!a.codes_checked) {
-    launch_codes(a.q, a.q_off, a.n, w.st, s);
-    launch_codes(a.t, a.t_off, a.n, w.st, s);
+    launch_codes(a.q, a.q_off, a.n, w.st, 0, s);
+    launch_codes(a.t, a.t_off, a.n, w.st, 0, s);
   }
   launch_scan(w.hist, w.cursor, w.cls_range, s);
   launch_scatter(a.n, a.q_off, qe, a.t_off, te, a.h0, a.pid, w.keys, w.cursor, w.desc, w.st,

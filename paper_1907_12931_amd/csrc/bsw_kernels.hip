@@ -1397,9 +1397,13 @@ void launch_prep(int64_t n, const uint8_t* q, const uint8_t* t, const uint64_t* 
                      hist, st);
 }
 
+// bytes = the sequence bytes when the host knows them (sizes the grid at
+// 4 KiB per group), or 0 for the full grid
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_codes, dim3(4096), dim3(256), 0, s, seq, off, n, st);
+                  uint64_t bytes, hipStream_t s) {
+  uint64_t blocks = bytes ? (bytes + 4095) / 4096 : 4096;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_codes, dim3((unsigned)blocks), dim3(256), 0, s, seq, off, n, st);
 }
 
 void launch_scan(const uint32_t* hist, uint32_t* cursor, long long* cls_range,

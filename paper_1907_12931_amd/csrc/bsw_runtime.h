@@ -47,7 +47,7 @@ hipStream_t ctx_stream(const bsw_ctx* c);
 
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
-                  hipStream_t s);
+                  uint64_t bytes, hipStream_t s);
 void launch_assemble(const ReqSlice* tab, int m, int64_t n, uint64_t* qb, uint64_t* qe,
                      uint64_t* tb, uint64_t* te, int32_t* h0, uint8_t* pid, hipStream_t s);
 

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -111,11 +112,14 @@ struct Req {
   Clock::time_point t_submit, t_admit, t_done;
 };
 
+enum SlotState { SLOT_FREE, SLOT_RUNNING, SLOT_COPYING };
+
 struct Slot {
   bsw_ctx* ctx = nullptr;
   hipStream_t s = nullptr;
   hipEvent_t done = nullptr;
-  bool busy = false;
+  std::atomic<int> state{SLOT_FREE};
+  bool want_diag = false;  // some request of the batch asked for diagnostics
   std::vector<Req*> reqs;
   int64_t n = 0;
   // device: assembled batch arrays and the request table
@@ -136,13 +140,16 @@ struct bsw_server {
   char* arena_base = nullptr;
   Arena arena;
   hipStream_t up = nullptr;  // uploads and code checks
-  std::vector<Slot> slots;
+  std::deque<Slot> slots;  // a deque: slots hold atomics and never move
   std::vector<hipEvent_t> free_events;
   std::vector<Status*> free_status;
   std::vector<Status*> status_blocks;  // pinned allocations (freed at the end)
 
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_copy;
+  std::deque<int> copy_q;  // finished slots whose results wait to be handed out
+  bool copier_stop = false;
+  std::thread copier;
   std::deque<Req*> pending;   // submitted, waiting for admission
   std::deque<Req*> admitted;  // admitted, not yet in a batch (arrival order)
   std::unordered_map<uint64_t, Req*> by_ticket;
@@ -237,8 +244,8 @@ int upload(bsw_server* v, Req* r) {
     SRVCHK(hipMemcpyAsync(base + r->o_pid, r->pid, (size_t)r->n, hipMemcpyHostToDevice, s));
   // the code check indexes seq[off[k]] with the caller's offsets, so the
   // bytes are addressed through a base shifted back by the first offset
-  launch_codes(dq - r->q_off[0], dqo, r->n, st, s);
-  launch_codes(dt - r->t_off[0], dto, r->n, st, s);
+  launch_codes(dq - r->q_off[0], dqo, r->n, st, r->qbytes, s);
+  launch_codes(dt - r->t_off[0], dto, r->n, st, r->tbytes, s);
   SRVCHK(hipGetLastError());
   SRVCHK(hipMemcpyAsync(r->h_st, st, sizeof(Status), hipMemcpyDeviceToHost, s));
   SRVCHK(hipEventRecord(r->ready, s));
@@ -321,9 +328,13 @@ int launch_batch(bsw_server* v, Slot& sl) {
   const Args a = {n,  ab,  qb,   ab, tb, h0, pid, (int32_t)v->params.size(),
                   out, diag, qe, te, true};
   if ((rc = ctx_enqueue(sl.ctx, a, s))) return rc;
-  SRVCHK(hipMemcpyAsync(sl.h_res, out, 40 * (size_t)n, hipMemcpyDeviceToHost, s));
+  sl.want_diag = false;
+  for (Req* r : sl.reqs) sl.want_diag = sl.want_diag || r->diag;
+  // results, then diagnostics (contiguous after them) when asked for
+  SRVCHK(hipMemcpyAsync(sl.h_res, out, (sl.want_diag ? 40 : 24) * (size_t)n,
+                        hipMemcpyDeviceToHost, s));
   SRVCHK(hipEventRecord(sl.done, s));
-  sl.busy = true;
+  sl.state = SLOT_RUNNING;
   return BSW_OK;
 }
 
@@ -374,7 +385,25 @@ void complete_slot(bsw_server* v, Slot& sl) {
   }
   v->cv_done.notify_all();
   sl.reqs.clear();
-  sl.busy = false;
+  sl.state = SLOT_FREE;
+  v->cv_work.notify_one();
+}
+
+// Hands finished batches' results to their requests, so that the copies
+// into the callers' buffers never hold up the scheduler.
+void copier(bsw_server* v) {
+  (void)hipSetDevice(v->opts.device);
+  for (;;) {
+    int k;
+    {
+      std::unique_lock<std::mutex> lk(v->mu);
+      v->cv_copy.wait(lk, [&] { return !v->copy_q.empty() || v->copier_stop; });
+      if (v->copy_q.empty()) return;
+      k = v->copy_q.front();
+      v->copy_q.pop_front();
+    }
+    complete_slot(v, v->slots[k]);
+  }
 }
 
 void scheduler(bsw_server* v) {
@@ -399,7 +428,7 @@ void scheduler(bsw_server* v) {
         to_upload.push_back(r);
       }
       bool busy = false;
-      for (auto& sl : v->slots) busy = busy || sl.busy;
+      for (auto& sl : v->slots) busy = busy || sl.state != SLOT_FREE;
       if (v->stop && v->pending.empty() && v->admitted.empty() && !busy) break;
       if (to_upload.empty() && !busy && v->admitted.empty())
         v->cv_work.wait_for(lk, std::chrono::milliseconds(5));
@@ -415,15 +444,22 @@ void scheduler(bsw_server* v) {
       }
       progress = true;
     }
-    // 2. completion
-    for (auto& sl : v->slots)
-      if (sl.busy && hipEventQuery(sl.done) == hipSuccess) {
-        complete_slot(v, sl);
+    // 2. completion: finished slots go to the copier
+    for (size_t k = 0; k < v->slots.size(); ++k) {
+      Slot& sl = v->slots[k];
+      if (sl.state == SLOT_RUNNING && hipEventQuery(sl.done) == hipSuccess) {
+        sl.state = SLOT_COPYING;
+        {
+          std::lock_guard<std::mutex> g(v->mu);
+          v->copy_q.push_back((int)k);
+        }
+        v->cv_copy.notify_one();
         progress = true;
       }
+    }
     // 3. dispatch: a free slot takes every ready admitted request
     for (auto& sl : v->slots) {
-      if (sl.busy) continue;
+      if (sl.state != SLOT_FREE) continue;
       std::vector<Req*> batch;
       {
         std::lock_guard<std::mutex> g(v->mu);
@@ -461,7 +497,7 @@ void scheduler(bsw_server* v) {
           finish_req(v, r, rc, Clock::now());
         }
         sl.reqs.clear();
-        sl.busy = false;
+        sl.state = SLOT_FREE;
         v->sched_err = rc;
         v->cv_done.notify_all();
       }
@@ -528,7 +564,7 @@ int bsw_server_create(bsw_server** out, const bsw_server_opts* opts,
   co.min_lane_bits = o.min_lane_bits;
   co.path = BSW_PATH_BATCHED;
   co.no_graph = 1;  // every batch has its own shapes and pointers
-  v->slots.resize((size_t)o.max_inflight);
+  for (int k = 0; k < o.max_inflight; ++k) v->slots.emplace_back();
   for (auto& sl : v->slots) {
     if ((rc = bsw_ctx_create(&sl.ctx, &co))) break;
     if ((rc = ctx_set_params(sl.ctx, params, n_params))) break;
@@ -557,6 +593,7 @@ int bsw_server_create(bsw_server** out, const bsw_server_opts* opts,
     return set_error(rc, "%s", msg.c_str());
   }
   v->arena.reset(o.hbm_budget);
+  v->copier = std::thread(copier, v);
   v->th = std::thread(scheduler, v);
   *out = v;
   return BSW_OK;
@@ -570,6 +607,12 @@ void bsw_server_destroy(bsw_server* v) {
   }
   v->cv_work.notify_all();
   if (v->th.joinable()) v->th.join();
+  {
+    std::lock_guard<std::mutex> g(v->mu);
+    v->copier_stop = true;
+  }
+  v->cv_copy.notify_all();
+  if (v->copier.joinable()) v->copier.join();
   destroy_server(v);
 }
 
