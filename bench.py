@@ -191,7 +191,7 @@ def main():
                           tune_cache=tune_cache if path == bsw.PATH_BATCHED else None)
         if path == bsw.PATH_BATCHED and not tuned and not args.no_tune:
             # launch shapes from the autotuner, on this batch (untimed)
-            ms, shape = ctx.tune(dev, batch["scorings"], out, reps=2)
+            ms, shape = ctx.tune(dev, batch["scorings"], out, reps=4)
             tuned.update(shape, tune_best_ms=round(ms, 3))
             log(f"tuned: {tuned}")
         ctx.extend_device(dev, batch["scorings"], out, diag)  # cells + warm

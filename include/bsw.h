@@ -151,16 +151,18 @@ int bsw_extend_batch_device(bsw_ctx* ctx, int64_t n,
                             bsw_result* out, bsw_diag* diag,
                             void* stream, int32_t async);
 
-/* Autotuner of the batched path.  Runs the batched path eagerly over a
- * device batch (arguments as bsw_extend_batch_device; results are written
- * to out as by a normal call) once per candidate launch shape: side streams
- * the kernel classes are spread over (4, 2, 1), share of resident groups
- * per CU for the 8-bit classes (100%, 50%), and whether pairs whose score
- * bound needs 16 bits are tried at 8 bits first (yes, no).  Each candidate
- * gets one warm-up call and reps (1..100) timed calls; the fastest device
- * time wins.  The winner is used by every later batched call of the context
- * with the same band limit and gap symmetry, and is stored in tune_cache
- * when one is set.  *best_ms (nullable) receives its time.  Blocking. */
+/* Autotuner of the batched path.  Runs the batched path over a device batch
+ * (arguments as bsw_extend_batch_device; results are written to out as by
+ * a normal call) once per candidate launch shape: side streams the kernel
+ * classes are spread over (4, 2, 1), share of resident groups per CU for
+ * the 8-bit classes (100%, 50%), and whether pairs whose score bound needs
+ * 16 bits are tried at 8 bits first (yes, no).  Each candidate runs
+ * eagerly: one warm-up call, then reps (1..100) timed calls; the lowest
+ * median device time wins, and a shape must beat the default by more than
+ * 1%.  The winner is used
+ * by every later batched call of the context with the same band limit and
+ * gap symmetry, and is stored in tune_cache when one is set.  *best_ms
+ * (nullable) receives its time.  Blocking. */
 int bsw_ctx_tune(bsw_ctx* ctx, int64_t n, const uint8_t* q, const uint64_t* q_off,
                  const uint8_t* t, const uint64_t* t_off, const int32_t* h0,
                  const uint8_t* param_id, const bsw_params* params, int32_t n_params,
