@@ -1,0 +1,132 @@
+"""Pins of the read-level seed extension reference (oracle.seeds).
+
+Each expected value follows from the method's definition by hand: exact
+matches grow the score by the match score per base, a mismatch costs 4, a
+gap of length k costs 6 + k (default scoring), and the end-of-read choice
+keeps the read end only when its score is within the end bonus of the best.
+"""
+import numpy as np
+import pytest
+
+from paper_1907_12931_amd import synth
+
+
+@pytest.fixture(scope="module")
+def seeds_mod(oracle_lib):
+    from oracle import seeds
+    return seeds
+
+
+def make(seeds_mod, read_list, ref, seed_rows):
+    ql = [len(r) for r in read_list]
+    reads = np.concatenate([np.asarray(r, np.uint8) for r in read_list])
+    off = np.zeros(len(ql) + 1, np.uint64)
+    off[1:] = np.cumsum(ql)
+    s = np.zeros(len(seed_rows), dtype=seeds_mod.SEED_DTYPE)
+    for k, (read, qb, qe, rb, h0) in enumerate(seed_rows):
+        s[k] = (read, qb, qe, h0, rb)
+    return reads, off, np.asarray(ref, np.uint8), s
+
+
+# (read length, reference position, qb, qe); the third clips the left
+# reference window at 0, the fourth the right window at the reference end
+CASES_EXACT = [(150, 300, 40, 80), (101, 1200, 1, 100), (250, 50, 120, 121),
+               (100, 1900, 10, 20)]
+
+
+def test_exact_read_reaches_both_ends(seeds_mod):
+    rng = np.random.default_rng(1)
+    ref = rng.integers(0, 4, 2000)
+    rows, reads = [], []
+    for k, (L, P, qb, qe) in enumerate(CASES_EXACT):
+        reads.append(ref[P:P + L])
+        rows.append((k, qb, qe, P + qb, qe - qb))
+    r, off, rf, s = make(seeds_mod, reads, ref, rows)
+    out = seeds_mod.extend_seeds(r, off, rf, s, synth.BWA_DEFAULT)
+    for k, (L, P, qb, qe) in enumerate(CASES_EXACT):
+        o = out[k]
+        assert (o["score"], o["qbeg"], o["qend"], o["rbeg"], o["rend"]) == (L, 0, L, P, P + L)
+        assert o["how"] == seeds_mod.READ_END | seeds_mod.READ_END << 2
+
+
+def test_seed_covering_the_read_is_not_extended(seeds_mod):
+    rng = np.random.default_rng(2)
+    ref = rng.integers(0, 4, 500)
+    r, off, rf, s = make(seeds_mod, [ref[100:160]], ref, [(0, 0, 60, 100, 60)])
+    o = seeds_mod.extend_seeds(r, off, rf, s, synth.BWA_DEFAULT)[0]
+    assert (o["score"], o["qbeg"], o["qend"], o["rbeg"], o["rend"]) == (60, 0, 60, 100, 160)
+    assert o["how"] == seeds_mod.NONE | seeds_mod.NONE << 2
+
+
+def test_mismatching_prefix_keeps_the_seed_start(seeds_mod):
+    # read = 10 x A, then ref[200:260]; the reference before the seed is all
+    # C: every path to the read start consumes 10 bases by mismatches or an
+    # insertion (at least 6 + 10), so the left end stays at the seed
+    ref = np.concatenate([np.full(200, 1), np.random.default_rng(3).integers(0, 4, 300)])
+    read = np.concatenate([np.zeros(10, int), ref[200:260]])
+    r, off, rf, s = make(seeds_mod, [read], ref, [(0, 10, 40, 200, 30)])
+    o = seeds_mod.extend_seeds(r, off, rf, s, synth.BWA_DEFAULT)[0]
+    assert (o["qbeg"], o["rbeg"]) == (10, 200)
+    assert o["how"] & 3 == seeds_mod.LOCAL
+    # the right side is exact: read[40:70] = ref[230:260], 30 more bases on
+    # top of the kept left score 30
+    assert (o["score"], o["qend"], o["rend"]) == (60, 70, 260)
+
+
+@pytest.mark.parametrize("bonus,left_read_end", [(5, True), (4, False), (3, False)])
+def test_end_bonus_decides_the_left_end(seeds_mod, bonus, left_read_end):
+    # read[0] mismatches the reference, read[1:] matches it exactly: the best
+    # left cell stops one base short (score h0 + qb - 1); reaching the read
+    # start costs the mismatch, 4, so the read end is kept only if 4 < bonus
+    rng = np.random.default_rng(4)
+    ref = rng.integers(0, 4, 600)
+    P, L, qb, qe, h0 = 200, 120, 30, 60, 30
+    read = ref[P:P + L].copy()
+    read[0] = (read[0] + 1) % 4
+    sc = synth.scoring(end_bonus=bonus)
+    r, off, rf, s = make(seeds_mod, [read], ref, [(0, qb, qe, P + qb, h0)])
+    o = seeds_mod.extend_seeds(r, off, rf, s, sc)[0]
+    if left_read_end:
+        assert (o["qbeg"], o["rbeg"]) == (0, P) and o["how"] & 3 == seeds_mod.READ_END
+        left = h0 + qb - 5
+    else:
+        assert (o["qbeg"], o["rbeg"]) == (1, P + 1) and o["how"] & 3 == seeds_mod.LOCAL
+        left = h0 + qb - 1
+    # right side exact to the read end
+    assert (o["score"], o["qend"], o["rend"]) == (left + L - qe, L, P + L)
+
+
+@pytest.mark.parametrize("bonus,right_read_end", [(5, True), (4, False)])
+def test_end_bonus_decides_the_right_end(seeds_mod, bonus, right_read_end):
+    rng = np.random.default_rng(5)
+    ref = rng.integers(0, 4, 600)
+    P, L, qb, qe, h0 = 100, 90, 0, 40, 40
+    read = ref[P:P + L].copy()
+    read[L - 1] = (read[L - 1] + 2) % 4
+    sc = synth.scoring(end_bonus=bonus)
+    r, off, rf, s = make(seeds_mod, [read], ref, [(0, qb, qe, P + qb, h0)])
+    o = seeds_mod.extend_seeds(r, off, rf, s, sc)[0]
+    best = h0 + (L - 1 - qe)
+    if right_read_end:
+        assert (o["score"], o["qend"], o["rend"]) == (best - 4, L, P + L)
+    else:
+        assert (o["score"], o["qend"], o["rend"]) == (best, L - 1, P + L - 1)
+
+
+def test_left_extension_is_bsw_on_the_reversed_prefix(seeds_mod, oracle_lib):
+    """The left side equals one BSW call written out by hand: reversed read
+    prefix, reversed reference window of qb + w bases before the seed."""
+    rng = np.random.default_rng(6)
+    ref = rng.integers(0, 5, 3000).astype(np.uint8)
+    read = np.concatenate([rng.integers(0, 4, 70), ref[1500:1580]]).astype(np.uint8)
+    qb, qe, rb, h0 = 90, 110, 1520, 20
+    r, off, rf, s = make(seeds_mod, [read], ref, [(0, qb, qe, rb, h0)])
+    o = seeds_mod.extend_seeds(r, off, rf, s, synth.BWA_DEFAULT)[0]
+    q = read[:qb][::-1].copy()
+    t = ref[rb - qb - 100:rb][::-1].copy()
+    vals, _ = oracle_lib.extend_one(q, t, h0, synth.BWA_DEFAULT)
+    res = dict(zip(oracle_lib.RESULT_DTYPE.names, vals))
+    if res["gscore"] > 0 and res["gscore"] > res["score"] - 5:
+        assert (o["qbeg"], o["rbeg"]) == (0, rb - res["gtle"])
+    else:
+        assert (o["qbeg"], o["rbeg"]) == (qb - res["qle"], rb - res["tle"])
