@@ -139,6 +139,44 @@ def serve(bsw, synth, batch, host, capacity, rho, n_requests, seed=3):
             "gcups": round(st["gcups"], 2), "window_s": round(st["window_s"], 3)}
 
 
+def seed_driver(bsw, synth, torch, np, tune_cache, steps, warmup):
+    """Read-level seed extension (left, end choice, right) over the seed
+    benchmark workload, device-resident, reversed reference supplied."""
+    t0 = time.time()
+    sw = synth.seed_workload(**synth.SEED_BENCH)
+    ns, nr = len(sw["seeds"]), len(sw["read_off"]) - 1
+    log(f"generated {nr} reads, {ns} seeds in {time.time() - t0:.1f}s")
+    dev = bsw.seeds_to_device(sw["reads"], sw["read_off"], sw["ref"], sw["seeds"],
+                              with_ref_rev=True)
+    out = torch.empty(ns * bsw.SEED_RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    ctx = bsw.Context(tune_cache=tune_cache)
+    for _ in range(max(1, warmup)):
+        ctx.extend_seeds_device(dev, sw["scoring"], out)
+    cells = ctx.last_cells()
+    torch.cuda.synchronize()
+    tms = []
+    t = time.perf_counter()
+    for _ in range(steps):
+        ctx.extend_seeds_device(dev, sw["scoring"], out)
+        tms.append(ctx.last_timing())
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / steps
+    assert ctx.last_cells() == cells
+    ctx.close()
+    tm = np.mean(np.asarray(tms), axis=0)
+    leg = {"value": round(ns / wall, 1), "unit": "seeds/s",
+           "reads_per_s": round(nr / wall, 1), "gcups": round(cells / wall / 1e9, 2),
+           "ms_per_step": round(wall * 1e3, 3), "device_ms": round(float(tm[0]), 3),
+           "left_ms": round(float(tm[1]), 3), "right_ms": round(float(tm[2]), 3),
+           "dp_launches": int(tm[3]),
+           "workload": f"{nr} reads x {synth.SEED_BENCH.get('read_len', 151)} bp from a "
+                       f"{len(sw['ref'])}-base random reference, 1-5% substitutions, "
+                       f"0.1-1% indels, 1% N; {ns} seeds (exact runs >= 19 bp, <= 3 per "
+                       "read); BWA default scoring; reversed reference supplied",
+           "seeds": ns, "reads": nr, "cells": int(cells)}
+    return leg, sw
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +186,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-seeds", action="store_true",
+                    help="skip the read-level seed driver leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shapes (skip the autotuner)")
@@ -245,6 +285,12 @@ def main():
                    for r in (0.5, 0.8)}
         log(f"serving: {serving}")
 
+    seeds_leg = None
+    if not args.no_seeds:
+        seeds_leg, sw = seed_driver(bsw, synth, torch, np, tune_cache, args.steps,
+                                    args.warmup)
+        log(f"seed driver: {seeds_leg}")
+
     # dominant kernel: the DP launch with the largest device time; its
     # algorithmic work is its settled cells x OPS_PER_CELL int32 operations
     dom, dk = max(p["kernels"].items(), key=lambda kv: kv[1]["ms"])
@@ -287,6 +333,19 @@ def main():
                "sample": f"{m} random pairs of the {n}-pair batch, "
                          f"{int(sd['cells'].sum())} cells, {dt:.1f} s"}
         log(f"cpu: {cpu}")
+        if seeds_leg is not None:
+            from oracle import seeds as oseeds
+            ns = len(sw["seeds"])
+            m = min(ns, 40000)
+            idx = np.sort(rng.choice(ns, size=m, replace=False))
+            t = time.perf_counter()
+            oseeds.extend_seeds(sw["reads"], sw["read_off"], sw["ref"], sw["seeds"][idx],
+                                sw["scoring"], n_threads=threads)
+            dt = time.perf_counter() - t
+            seeds_leg["cpu_baseline"] = {
+                "value": round(m / dt, 1), "unit": "seeds/s", "cores": threads,
+                "kind": "oracle", "sample": f"{m} random seeds of the {ns}, {dt:.1f} s"}
+            log(f"cpu seeds: {seeds_leg['cpu_baseline']}")
 
     res = {
         "metric": "GCUPS (bit-exact vs oracle) batched vs plain; p50/p99 latency under serving",
@@ -300,7 +359,8 @@ def main():
                    "pairs": n, "cells": cells, "path": "batched",
                    "dp_launches": b["dp_launches"], "graph": True, "tuned": tuned,
                    "prep_bin_ms": round(p["prep_ms"], 3)},
-        "plain": plain, "serving": serving, "roofline": roofline, "cpu_baseline": cpu,
+        "plain": plain, "serving": serving, "seed_driver": seeds_leg, "roofline": roofline,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
 

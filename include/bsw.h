@@ -183,6 +183,11 @@ int bsw_ctx_wait(bsw_ctx* ctx);
  * a graph replay has [0] only ([1] = [2] = 0).  Returns BSW_OK. */
 int bsw_ctx_last_timing(bsw_ctx* ctx, double out4[4]);
 
+/* Band cells settled by the last completed call (all of its BSW passes;
+ * the rerun of pairs that overflowed a narrow record width counts again).
+ * Returns BSW_OK. */
+int bsw_ctx_last_cells(bsw_ctx* ctx, int64_t* cells);
+
 /* Per-launch record of the last completed call's DP kernels: for launch k,
  * cls[k] = kernel class (see bsw_class_name), cells[k] = band cells the
  * launch settled, ms[k] = its device time from HIP events on the launch
@@ -273,6 +278,83 @@ int bsw_server_wait(bsw_server* srv, uint64_t ticket, int32_t timeout_ms);
 
 /* Fill *out; reset != 0 starts a new measurement window. */
 int bsw_server_stats(bsw_server* srv, bsw_server_report* out, int32_t reset);
+
+/* ------------------------------------------------------------------------
+ * Read-level seed extension: the step around BSW in the read mapper
+ * (Sec. 2: a seed, an exact match of read bases to the reference, is
+ * extended on both sides; Sec. 5.3.2: every seed is extended, and the
+ * removal of seeds the mapper would not have extended comes afterwards and
+ * is not part of this step).  For each seed, with w and end_bonus of the
+ * scoring set:
+ *  1. left: BSW on the reversed read prefix read[0, qb) against the
+ *     reversed reference window ref[max(0, rb - qb - w), rb), from the seed
+ *     score h0;
+ *  2. the end kept is the read start when gscore > 0 and
+ *     gscore > score - end_bonus (reaching the end of the read costs less
+ *     than the bonus), else the best cell; the kept score is h1;
+ *  3. right: BSW on read[qe, len) against ref[re, min(ref_len,
+ *     re + len - qe + w)) with re = rb + qe - qb, from h1; the end is kept
+ *     by the same rule.
+ * A side with nothing to extend (qb = 0, or qe = len) keeps the seed
+ * boundary and carries the score over; its BSW call sees an empty query and
+ * its result is not used.  The two BSW calls run the batched path of the
+ * context (never as a graph replay).
+ * ---------------------------------------------------------------------- */
+
+/* One seed (24 bytes): read[qb, qe) equals ref[rb, rb + qe - qb). */
+typedef struct bsw_seed {
+  int32_t read;   /* read index, 0 <= read < n_reads                      */
+  int32_t qb, qe; /* 0 <= qb <= qe <= read length                         */
+  int32_t h0;     /* seed score, 1..BSW_MAX_H0                            */
+  int64_t rb;     /* 0 <= rb, rb + qe - qb <= ref_len                     */
+} bsw_seed;
+
+/* Which end a side kept. */
+enum { BSW_END_LOCAL = 0, BSW_END_READ = 1, BSW_END_NONE = 2 };
+
+/* Result of one seed (32 bytes). */
+typedef struct bsw_seed_result {
+  int32_t score;      /* score after both sides                           */
+  int32_t qbeg, qend; /* extended read interval [qbeg, qend)              */
+  int32_t how;        /* left | right << 2, each a BSW_END_* value        */
+  int64_t rbeg, rend; /* extended reference interval [rbeg, rend)         */
+} bsw_seed_result;
+
+/* Host-memory form.  Reads are byte codes 0..4 concatenated, read i being
+ * reads[read_off[i] .. read_off[i+1]) (n_reads + 1 non-decreasing offsets,
+ * lengths <= BSW_MAX_LEN); ref holds ref_len codes 0..4.  params is one
+ * scoring set (as for bsw_extend_batch).  Every seed is checked on the host
+ * first (BSW_EINVAL names the first bad one, as does a reference window
+ * longer than BSW_MAX_LEN); a code > 4 in a read or in the reference fails
+ * the call on the device.  The reads, the reference and the seeds are
+ * copied to the device on every call.  Blocking; n = 0 is a no-op. */
+int bsw_extend_seeds(bsw_ctx* ctx, const uint8_t* reads, const uint64_t* read_off,
+                     int64_t n_reads, const uint8_t* ref, uint64_t ref_len,
+                     const bsw_seed* seeds, int64_t n, const bsw_params* params,
+                     bsw_seed_result* out);
+
+/* Device-memory form: reads (reads_len bytes), read_off, ref, ref_rev,
+ * seeds and out are device pointers; params is host memory.  ref_rev is
+ * the reference reversed (ref_rev[i] = ref[ref_len - 1 - i]), which a
+ * caller that extends many batches against one reference makes once; NULL
+ * makes the library reverse ref into its arena on every call.  The reads
+ * are reversed into the arena on every call.  Seeds, offsets and codes are
+ * checked on the device before any result is written; a bad one makes the
+ * call write nothing and return BSW_EINVAL naming the first bad seed (or
+ * read).  stream and async as for bsw_extend_batch_device; between an
+ * asynchronous call and bsw_ctx_wait the inputs must stay valid and
+ * bsw_ctx_wait returns the status.  Every byte of reads and ref must be a
+ * code 0..4.  Arena use per call: reads_len (+ ref_len without ref_rev)
+ * bytes, 160 bytes per seed and the BSW pipeline's own workspace.  After
+ * the call, bsw_ctx_last_timing gives [0] = the whole call, [1] = checks,
+ * reversal and the left side, [2] = the right side, [3] = DP launches of
+ * both sides; bsw_ctx_last_cells counts the cells of both sides;
+ * bsw_ctx_last_kernels lists the right side's launches. */
+int bsw_extend_seeds_device(bsw_ctx* ctx, const uint8_t* reads, uint64_t reads_len,
+                            const uint64_t* read_off, int64_t n_reads,
+                            const uint8_t* ref, const uint8_t* ref_rev, uint64_t ref_len,
+                            const bsw_seed* seeds, int64_t n, const bsw_params* params,
+                            bsw_seed_result* out, void* stream, int32_t async);
 
 /* Text of the calling thread's most recent error ("" if none). */
 const char* bsw_last_error(void);

@@ -62,6 +62,12 @@ class ServerReport(ctypes.Structure):
 RESULT_DTYPE = np.dtype([("score", "<i4"), ("qle", "<i4"), ("tle", "<i4"),
                          ("gtle", "<i4"), ("gscore", "<i4"), ("max_off", "<i4")])
 DIAG_DTYPE = np.dtype([("rows", "<i4"), ("stop", "<i4"), ("cells", "<i8")])
+# read-level seed extension (bsw_seed / bsw_seed_result)
+SEED_DTYPE = np.dtype([("read", "<i4"), ("qb", "<i4"), ("qe", "<i4"), ("h0", "<i4"),
+                       ("rb", "<i8")])
+SEED_RESULT_DTYPE = np.dtype([("score", "<i4"), ("qbeg", "<i4"), ("qend", "<i4"),
+                              ("how", "<i4"), ("rbeg", "<i8"), ("rend", "<i8")])
+END_LOCAL, END_READ, END_NONE = 0, 1, 2
 
 _lib = None
 _VP = ctypes.c_void_p
@@ -111,6 +117,15 @@ def lib():
         L.bsw_ctx_tune.argtypes = [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP,
                                    ctypes.POINTER(Params), ctypes.c_int32, _VP,
                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.bsw_ctx_last_cells.restype = ctypes.c_int
+        L.bsw_ctx_last_cells.argtypes = [_VP, ctypes.POINTER(ctypes.c_int64)]
+        L.bsw_extend_seeds.restype = ctypes.c_int
+        L.bsw_extend_seeds.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.c_uint64,
+                                       _VP, ctypes.c_int64, ctypes.POINTER(Params), _VP]
+        L.bsw_extend_seeds_device.restype = ctypes.c_int
+        L.bsw_extend_seeds_device.argtypes = [
+            _VP, _VP, ctypes.c_uint64, _VP, ctypes.c_int64, _VP, _VP, ctypes.c_uint64,
+            _VP, ctypes.c_int64, ctypes.POINTER(Params), _VP, _VP, ctypes.c_int32]
         L.bsw_ctx_tune_info.restype = ctypes.c_int
         L.bsw_ctx_tune_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
         L.bsw_server_create.restype = ctypes.c_int
@@ -219,6 +234,41 @@ class Context:
     def wait(self):
         _check(lib().bsw_ctx_wait(self._h))
 
+    def extend_seeds(self, reads, read_off, ref, seeds, scoring):
+        """Read-level seed extension from host memory (``bsw_extend_seeds``):
+        reads/ref are uint8 code arrays, read_off the n_reads + 1 offsets,
+        seeds a SEED_DTYPE array; returns SEED_RESULT_DTYPE records."""
+        reads = np.ascontiguousarray(reads, dtype=np.uint8)
+        read_off = np.ascontiguousarray(read_off, dtype=np.uint64)
+        ref = np.ascontiguousarray(ref, dtype=np.uint8)
+        seeds = np.ascontiguousarray(seeds, dtype=SEED_DTYPE)
+        out = np.zeros(len(seeds), dtype=SEED_RESULT_DTYPE)
+        params = make_params([scoring])
+        _check(lib().bsw_extend_seeds(
+            self._h, _ptr(reads), read_off.ctypes.data, len(read_off) - 1, _ptr(ref),
+            len(ref), _ptr(seeds), len(seeds), params, _ptr(out)))
+        return out
+
+    def extend_seeds_device(self, dev, scoring, out, stream=None, async_=False):
+        """Device form (``bsw_extend_seeds_device``): ``dev`` as made by
+        ``seeds_to_device``; ``out`` a torch tensor of n*32 bytes."""
+        n = dev["seeds"].numel() // SEED_DTYPE.itemsize
+        params = make_params([scoring])
+        rev = dev.get("ref_rev")
+        s = stream.cuda_stream if stream is not None else None
+        _check(lib().bsw_extend_seeds_device(
+            self._h, dev["reads"].data_ptr(), dev["reads"].numel(),
+            dev["read_off"].data_ptr(), dev["read_off"].numel() - 1,
+            dev["ref"].data_ptr(), rev.data_ptr() if rev is not None else None,
+            dev["ref"].numel(), dev["seeds"].data_ptr(), n, params, out.data_ptr(), s,
+            1 if async_ else 0))
+
+    def last_cells(self):
+        """Band cells settled by the last completed call (all its passes)."""
+        v = ctypes.c_int64(0)
+        _check(lib().bsw_ctx_last_cells(self._h, ctypes.byref(v)))
+        return v.value
+
     def tune(self, dev, scorings, out, reps=2):
         """Autotune the batched path's launch shapes on a device batch;
         returns (best_ms, shape dict)."""
@@ -267,6 +317,22 @@ def to_device(batch, device="cuda"):
             if a.dtype == np.uint64:
                 a = a.view(np.int64)
             dev[k] = torch.from_numpy(a).to(device)
+    return dev
+
+
+def seeds_to_device(reads, read_off, ref, seeds, device="cuda", with_ref_rev=False):
+    """Copy a seed workload (host arrays) into torch tensors on the GPU; the
+    reversed reference is made on the host when asked for."""
+    import torch
+    dev = {"reads": torch.from_numpy(np.ascontiguousarray(reads, dtype=np.uint8)).to(device),
+           "read_off": torch.from_numpy(
+               np.ascontiguousarray(read_off, dtype=np.uint64).view(np.int64)).to(device),
+           "ref": torch.from_numpy(np.ascontiguousarray(ref, dtype=np.uint8)).to(device),
+           "seeds": torch.from_numpy(
+               np.ascontiguousarray(seeds, dtype=SEED_DTYPE).view(np.uint8)).to(device)}
+    if with_ref_rev:
+        rev = np.ascontiguousarray(np.asarray(ref, dtype=np.uint8)[::-1])
+        dev["ref_rev"] = torch.from_numpy(rev).to(device)
     return dev
 
 

@@ -82,43 +82,6 @@ int fail(int code, const char* fmt, ...) {
                   "%s failed: %s", #expr, hipGetErrorString(e_));             \
   } while (0)
 
-// Device bytes a context may hold (0 = no cap) and holds.
-struct Budget {
-  size_t limit = 0;
-  size_t used = 0;
-};
-
-// A growable device buffer, counted against its context's budget.
-struct DevBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-  Budget* b = nullptr;
-  int ensure(size_t bytes) {
-    if (bytes <= cap) return BSW_OK;
-    // grow by at least half, so that slowly rising sizes reallocate (and
-    // synchronise the device in hipFree) only a few times
-    const size_t want = std::max(std::max(bytes, cap + cap / 2), (size_t)1 << 20);
-    if (b && b->limit && b->used - cap + want > b->limit)
-      return fail(BSW_ETOOBIG, "the call needs %zu more device bytes than the context's "
-                  "budget of %zu", b->used - cap + want - b->limit, b->limit);
-    release();
-    if (hipMalloc(&p, want) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      return fail(BSW_ENOMEM, "device allocation of %zu bytes failed", want);
-    }
-    cap = want;
-    if (b) b->used += cap;
-    return BSW_OK;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    if (b) b->used -= cap;
-    p = nullptr;
-    cap = 0;
-  }
-};
-
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up for n pairs.
@@ -267,9 +230,12 @@ struct bsw_ctx {
   int occc[2][NCLS][80] = {};
   bool pending = false;
   hipStream_t pending_stream = nullptr;
+  int (*pending_done)(bsw_ctx*) = nullptr;  // completion check of that call
+  SeedState* seed = nullptr;                // read-level seed driver
   bool graph_call = false;  // the last call ran as a graph replay
   Status* last_st = nullptr;  // device status block of the last call
   double timing[4] = {0, 0, 0, 0};
+  unsigned long long last_cells = 0;  // band cells of the last finished call
   // captured batched pipeline and what it was captured for
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey;
@@ -722,6 +688,8 @@ int finish_call(bsw_ctx* c) {
     return fail(BSW_EINVAL, "pair %llu is invalid (lengths, h0, param_id or a code > 4)",
                 ~(unsigned long long)c->h_status->first_bad_inv);
   record_timing(c);
+  c->last_cells = 0;
+  for (int k = 0; k <= NCLS; ++k) c->last_cells += c->h_status->cls_cells[k];
   return BSW_OK;
 }
 
@@ -769,6 +737,34 @@ int ctx_enqueue(bsw_ctx* c, const Args& a, hipStream_t s) {
 }
 
 int ctx_finish(bsw_ctx* c) { return finish_call(c); }
+
+int ctx_enqueue_eager(bsw_ctx* c, const Args& a, hipStream_t s) {
+  const int32_t saved = c->opts.no_graph;
+  c->opts.no_graph = 1;
+  const int rc = run_pipeline(c, a, s);
+  c->opts.no_graph = saved;
+  return rc;
+}
+
+Status* ctx_status_dev(const bsw_ctx* c) { return c->last_st; }
+
+Budget* ctx_budget(bsw_ctx* c) { return &c->budget; }
+
+int ctx_launches(const bsw_ctx* c) { return c->n_launch; }
+
+double* ctx_timing(bsw_ctx* c) { return c->timing; }
+
+void ctx_add_cells(bsw_ctx* c, unsigned long long cells) { c->last_cells += cells; }
+
+int ctx_set_device(bsw_ctx* c) { return set_device(c); }
+
+void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*)) {
+  c->pending = true;
+  c->pending_stream = s;
+  c->pending_done = done;
+}
+
+SeedState*& ctx_seed_state(bsw_ctx* c) { return c->seed; }
 
 unsigned long long ctx_last_cells(const bsw_ctx* c) {
   unsigned long long sum = 0;
@@ -859,6 +855,8 @@ void bsw_ctx_destroy(bsw_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->pending) (void)hipStreamSynchronize(c->pending_stream);
+  seed_state_free(c->seed);
   c->ws.release();
   c->in.release();
   c->res.release();
@@ -905,8 +903,7 @@ int bsw_extend_batch_device(bsw_ctx* c, int64_t n, const uint8_t* q,
   rc = run_pipeline(c, a, s);
   if (rc) return rc;
   if (async) {
-    c->pending = true;
-    c->pending_stream = s;
+    ctx_set_pending(c, s, finish_call);
     return BSW_OK;
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -992,7 +989,7 @@ int bsw_ctx_wait(bsw_ctx* c) {
   if (!c->pending) return BSW_OK;
   c->pending = false;
   HIPCHK(hipStreamSynchronize(c->pending_stream));
-  return finish_call(c);
+  return c->pending_done ? c->pending_done(c) : finish_call(c);
 }
 
 int bsw_ctx_last_kernels(bsw_ctx* c, int32_t* cls, int64_t* cells, double* ms,
@@ -1014,6 +1011,12 @@ const char* bsw_class_name(int32_t cls) {
       "lane16_q128", "lane16_q256", "lane32_q32", "lane32_q64", "lane32_q128",
       "lane32_q256", "long", "rerun"};
   return cls >= 0 && cls <= NCLS ? names[cls] : "?";
+}
+
+int bsw_ctx_last_cells(bsw_ctx* c, int64_t* cells) {
+  if (!c || !cells) return fail(BSW_EINVAL, "NULL argument");
+  *cells = (int64_t)c->last_cells;
+  return BSW_OK;
 }
 
 int bsw_ctx_last_timing(bsw_ctx* c, double out4[4]) {

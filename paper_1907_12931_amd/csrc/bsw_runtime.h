@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "../../include/bsw.h"
@@ -31,6 +32,43 @@ struct Args {
 // Set the calling thread's error text; returns code.
 int set_error(int code, const char* fmt, ...);
 
+// Device bytes a context may hold (0 = no cap) and holds.
+struct Budget {
+  size_t limit = 0;
+  size_t used = 0;
+};
+
+// A growable device buffer, counted against its context's budget.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  Budget* b = nullptr;
+  int ensure(size_t bytes) {
+    if (bytes <= cap) return BSW_OK;
+    // grow by at least half, so that slowly rising sizes reallocate (and
+    // synchronise the device in hipFree) only a few times
+    const size_t want = std::max(std::max(bytes, cap + cap / 2), (size_t)1 << 20);
+    if (b && b->limit && b->used - cap + want > b->limit)
+      return set_error(BSW_ETOOBIG, "the call needs %zu more device bytes than the "
+                       "context's budget of %zu", b->used - cap + want - b->limit, b->limit);
+    release();
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return set_error(BSW_ENOMEM, "device allocation of %zu bytes failed", want);
+    }
+    cap = want;
+    if (b) b->used += cap;
+    return BSW_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    if (b) b->used -= cap;
+    p = nullptr;
+    cap = 0;
+  }
+};
+
 // Load a context's scoring table (validated).
 int ctx_set_params(bsw_ctx* c, const bsw_params* params, int32_t n_params);
 // Allocate a context's device buffers for calls of up to n pairs with its
@@ -44,6 +82,29 @@ int ctx_finish(bsw_ctx* c);
 // Band cells settled by the last finished call.
 unsigned long long ctx_last_cells(const bsw_ctx* c);
 hipStream_t ctx_stream(const bsw_ctx* c);
+// As ctx_enqueue, but never captured into or replayed from a graph (for
+// drivers that run the pipeline several times per call on other buffers).
+int ctx_enqueue_eager(bsw_ctx* c, const Args& a, hipStream_t s);
+// Device status block of the last enqueued call (valid until the next).
+Status* ctx_status_dev(const bsw_ctx* c);
+Budget* ctx_budget(bsw_ctx* c);
+// DP launches the last enqueued call made.
+int ctx_launches(const bsw_ctx* c);
+// bsw_ctx_last_timing's four values, and the band cells bsw_ctx_last_cells
+// reports, of the last finished call (a driver adjusts them after
+// ctx_finish).
+double* ctx_timing(bsw_ctx* c);
+void ctx_add_cells(bsw_ctx* c, unsigned long long cells);
+int ctx_set_device(bsw_ctx* c);
+// Mark the context as having an asynchronous call in flight on s whose
+// completion is checked by done (bsw_ctx_wait calls it).
+void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*));
+
+// State of the read-level seed driver, owned by the context (created on
+// first use, released with the context).
+struct SeedState;
+SeedState*& ctx_seed_state(bsw_ctx* c);
+void seed_state_free(SeedState* s);
 
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,

@@ -327,6 +327,102 @@ def serving_requests(n_requests=2000, seed=3, lo=1000, hi=100_000):
     return sizes.astype(np.int64)
 
 
+# seeds as the read-level driver takes them (one record per seed)
+SEED_FIELDS = np.dtype([("read", "<i4"), ("qb", "<i4"), ("qe", "<i4"), ("h0", "<i4"),
+                        ("rb", "<i8")])
+
+
+def _reads_chunk(rng, ref, m, read_len, min_seed, max_seeds, p_n):
+    """m reads drawn from ref by a per-position walk that records where each
+    read base came from, and the seeds of each read: its exact runs along
+    one reference diagonal of at least min_seed bases (longest first, at
+    most max_seeds)."""
+    L = read_len
+    nref = len(ref)
+    p_sub = rng.uniform(0.01, 0.05, size=(m, 1))
+    p_ind = rng.uniform(0.001, 0.01, size=(m, 1))
+    # insertion runs: positions [i, i + k) of the read come from nowhere
+    ins_start = rng.random((m, L)) < p_ind / 2
+    ins = np.zeros((m, L + 1), dtype=np.int32)
+    r_i, c_i = np.nonzero(ins_start)
+    k = rng.geometric(0.5, size=len(r_i))
+    np.add.at(ins, (r_i, c_i), 1)
+    np.add.at(ins, (r_i, np.minimum(c_i + k, L)), -1)
+    inserted = np.cumsum(ins[:, :L], axis=1) > 0
+    # deletions: k reference bases skipped before position i
+    adv = (~inserted).astype(np.int64)
+    del_start = (rng.random((m, L)) < p_ind / 2) & ~inserted
+    adv[del_start] += rng.geometric(0.5, size=int(del_start.sum()))
+    span = adv.sum(axis=1)
+    start = rng.integers(0, max(1, nref - int(span.max()) - 1), size=m)
+    src = start[:, None] + np.cumsum(adv, axis=1) - 1
+    src = np.minimum(src, nref - 1)
+    base = ref[src]
+    sub = (rng.random((m, L)) < p_sub) & ~inserted
+    base = np.where(sub, (base + rng.integers(1, 4, size=(m, L))) % 4, base)
+    base = np.where(inserted, rng.integers(0, 4, size=(m, L)), base).astype(np.uint8)
+    if p_n > 0:
+        base[rng.random((m, L)) < p_n] = 4
+    exact = ~inserted & (base == ref[src]) & (base < 4)
+    # a run continues while exact and on the same diagonal
+    cont = np.zeros((m, L), dtype=bool)
+    cont[:, 1:] = exact[:, 1:] & exact[:, :-1] & (src[:, 1:] == src[:, :-1] + 1)
+    begin = exact & ~cont
+    end = np.zeros((m, L), dtype=bool)  # last position of a run
+    end[:, :-1] = exact[:, :-1] & ~cont[:, 1:]
+    end[:, -1] = exact[:, -1]
+    br, bc = np.nonzero(begin)
+    er, ec = np.nonzero(end)
+    qlen = ec + 1 - bc
+    keep = qlen >= min_seed
+    br, bc, ec, qlen = br[keep], bc[keep], ec[keep], qlen[keep]
+    # longest first per read, at most max_seeds
+    order = np.lexsort((bc, -qlen, br))
+    br, bc, ec, qlen = br[order], bc[order], ec[order], qlen[order]
+    first = np.searchsorted(br, br, side="left")
+    rank = np.arange(len(br)) - first
+    keep = rank < max_seeds
+    br, bc, ec, qlen = br[keep], bc[keep], ec[keep], qlen[keep]
+    order = np.lexsort((bc, br))  # read order, then position
+    br, bc, ec, qlen = br[order], bc[order], ec[order], qlen[order]
+    seeds = np.zeros(len(br), dtype=SEED_FIELDS)
+    seeds["read"] = br
+    seeds["qb"] = bc
+    seeds["qe"] = ec + 1
+    seeds["h0"] = qlen
+    seeds["rb"] = src[br, bc]
+    return base.reshape(-1), seeds
+
+
+def seed_workload(n_reads=2000, seed=5, read_len=151, ref_len=1 << 20, min_seed=19,
+                  max_seeds=3, p_n=0.01, p_n_ref=0.0005, chunk=50_000):
+    """Reads and seeds for the read-level driver: a uniform random reference
+    of ref_len codes (N at rate p_n_ref), reads of read_len bases drawn from
+    it with 1-5% substitutions and 0.1-1% indels (geometric length, mean 2)
+    per read and N at rate p_n, and up to max_seeds seeds per read (exact
+    runs of at least min_seed bases on one diagonal, h0 = their length).
+    Reads with no such run have no seed.  Default scoring BWA_DEFAULT."""
+    rngs = _chunk_rngs(seed, (n_reads + chunk - 1) // chunk + 1)
+    ref = _sprinkle_n(rngs[0], _random_bases(rngs[0], ref_len), p_n_ref)
+    reads, seeds = [], []
+    done = 0
+    for i, rng in enumerate(rngs[1:]):
+        m = min(chunk, n_reads - done)
+        r, sd = _reads_chunk(rng, ref, m, read_len, min_seed, max_seeds, p_n)
+        sd["read"] += done
+        reads.append(r)
+        seeds.append(sd)
+        done += m
+    read_off = np.arange(n_reads + 1, dtype=np.uint64) * np.uint64(read_len)
+    return {"reads": np.concatenate(reads), "read_off": read_off, "ref": ref,
+            "seeds": np.concatenate(seeds), "scoring": BWA_DEFAULT}
+
+
+# the read-level driver's benchmark workload: 500,000 reads of 151 bases
+# drawn from a 64 Mbase reference (about 1.3 M seeds)
+SEED_BENCH = dict(n_reads=500_000, seed=5, ref_len=1 << 26)
+
+
 WORKLOADS = {
     "plain_small": plain_small,
     "read_scale": read_scale,

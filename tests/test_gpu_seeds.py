@@ -1,0 +1,174 @@
+"""Parity of the read-level seed driver (bsw_extend_seeds, and the device
+form bsw_extend_seeds_device) with the CPU reference oracle.seeds, field by
+field, on seeded synthetic reads and seeds; edge cases and error paths."""
+import numpy as np
+import pytest
+
+from paper_1907_12931_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("score", "qbeg", "qend", "how", "rbeg", "rend")
+
+
+@pytest.fixture(scope="module")
+def bsw():
+    from paper_1907_12931_amd import bsw as b
+    return b
+
+
+@pytest.fixture(scope="module")
+def ctx(bsw):
+    with bsw.Context() as c:
+        yield c
+
+
+def reference(w, seeds=None, scoring=None):
+    from oracle import seeds as oseeds
+    sd = w["seeds"] if seeds is None else seeds
+    return oseeds.extend_seeds(w["reads"], w["read_off"], w["ref"],
+                               np.asarray(sd, dtype=oseeds.SEED_DTYPE),
+                               scoring or w["scoring"])
+
+
+def assert_same(got, want, what=""):
+    assert len(got) == len(want)
+    for f in FIELDS:
+        bad = np.nonzero(got[f] != want[f])[0]
+        assert len(bad) == 0, (f"{what} field {f}: {len(bad)} of {len(got)} differ; first "
+                               f"seed {bad[0]}: got {got[bad[0]]}, want {want[bad[0]]}")
+
+
+def run_device(bsw, ctx, w, with_rev=False, async_=False, scoring=None):
+    import torch
+    dev = bsw.seeds_to_device(w["reads"], w["read_off"], w["ref"], w["seeds"],
+                              with_ref_rev=with_rev)
+    n = len(w["seeds"])
+    out = torch.full((n * bsw.SEED_RESULT_DTYPE.itemsize,), 0x5a, dtype=torch.uint8,
+                     device="cuda")
+    ctx.extend_seeds_device(dev, scoring or w["scoring"], out, async_=async_)
+    if async_:
+        ctx.wait()
+    return out.cpu().numpy().view(bsw.SEED_RESULT_DTYPE)
+
+
+def test_host_form_matches_reference(bsw, ctx, oracle_lib):
+    w = synth.seed_workload(2000, seed=11)
+    print("seeds", len(w["seeds"]), flush=True)
+    got = ctx.extend_seeds(w["reads"], w["read_off"], w["ref"], w["seeds"], w["scoring"])
+    assert_same(got, reference(w))
+    t = ctx.last_timing()
+    assert t[0] > 0 and t[0] >= t[1] and t[3] >= 2
+    assert ctx.last_cells() > 0
+
+
+@pytest.mark.parametrize("with_rev,async_", [(False, False), (True, False), (True, True)])
+def test_device_form_matches_reference(bsw, ctx, oracle_lib, with_rev, async_):
+    w = synth.seed_workload(3000, seed=12, ref_len=200_000)
+    got = run_device(bsw, ctx, w, with_rev=with_rev, async_=async_)
+    assert_same(got, reference(w))
+
+
+def test_plain_path_matches_reference(bsw, oracle_lib):
+    w = synth.seed_workload(1500, seed=13)
+    with bsw.Context(path=bsw.PATH_PLAIN) as c:
+        got = c.extend_seeds(w["reads"], w["read_off"], w["ref"], w["seeds"], w["scoring"])
+    assert_same(got, reference(w))
+
+
+@pytest.mark.parametrize("sc", [synth.WIDE_B, synth.scoring(end_bonus=40),
+                                synth.scoring(end_bonus=0, zdrop=30),
+                                synth.scoring(2, -5, -2, 4, 2, w=30, zdrop=0, end_bonus=8)])
+def test_other_scorings(bsw, ctx, oracle_lib, sc):
+    w = synth.seed_workload(1200, seed=14)
+    # seed scores in the scoring's match units
+    w["seeds"]["h0"] *= int(np.asarray(sc["mat"]).reshape(25)[0])
+    got = ctx.extend_seeds(w["reads"], w["read_off"], w["ref"], w["seeds"], sc)
+    assert_same(got, reference(w, scoring=sc), str(sc))
+
+
+def edge_workload():
+    """Hand-made reads at the ends of a short reference, an empty read, a
+    read that is all N but for its seed, zero-length and whole-read seeds."""
+    rng = np.random.default_rng(15)
+    ref = rng.integers(0, 4, 700).astype(np.uint8)
+    ref[350:353] = 4
+    reads, seeds = [], []
+
+    def add(read, qb, qe, rb, h0):
+        seeds.append((len(reads), qb, qe, h0, rb))
+        reads.append(np.asarray(read, dtype=np.uint8))
+
+    add(ref[0:120], 30, 60, 30, 30)              # left window clipped at 0
+    add(ref[580:700], 40, 90, 620, 50)           # right window clipped at the end
+    add(ref[600:700], 0, 100, 600, 100)          # whole read, at the end
+    add(ref[0:90], 0, 25, 0, 25)                 # qb = 0 at the reference start
+    add(ref[200:320], 95, 120, 295, 25)          # qe = read length
+    add(np.zeros(0, np.uint8), 0, 0, 10, 7)      # empty read
+    add(ref[100:220], 50, 50, 150, 3)            # zero-length seed
+    r = ref[300:450].copy()                      # N in reference and read
+    r[:40] = 4
+    add(r, 60, 90, 360, 30)
+    r = ref[400:551].copy()
+    r[::7] = (r[::7] + 1) % 4                    # dense substitutions
+    add(r, 71, 76, 471, 5)
+    add(ref[0:151], 0, 0, 0, 1)                  # zero-length seed at 0
+    add(ref[549:700], 151, 151, 700, 1)          # zero-length seed at the end
+    ql = [len(x) for x in reads]
+    off = np.zeros(len(ql) + 1, np.uint64)
+    off[1:] = np.cumsum(ql)
+    sd = np.zeros(len(seeds), dtype=synth.SEED_FIELDS)
+    for k, s in enumerate(seeds):
+        sd[k] = s
+    return {"reads": np.concatenate(reads), "read_off": off, "ref": ref, "seeds": sd,
+            "scoring": synth.BWA_DEFAULT}
+
+
+def test_edge_cases(bsw, ctx, oracle_lib):
+    w = edge_workload()
+    want = reference(w)
+    assert_same(ctx.extend_seeds(w["reads"], w["read_off"], w["ref"], w["seeds"],
+                                 w["scoring"]), want, "host form")
+    assert_same(run_device(bsw, ctx, w, with_rev=False), want, "device form")
+    assert_same(run_device(bsw, ctx, w, with_rev=True), want, "device form, ref_rev")
+
+
+def test_bad_seed_is_rejected_and_nothing_written(bsw, ctx):
+    import torch
+    w = synth.seed_workload(300, seed=16)
+    bad = w["seeds"].copy()
+    bad[7]["qe"] = 152                             # past the read end
+    with pytest.raises(bsw.BswError) as ei:
+        ctx.extend_seeds(w["reads"], w["read_off"], w["ref"], bad, w["scoring"])
+    assert ei.value.code == bsw.EINVAL and "seed 7" in str(ei.value)
+    # device form: the check runs on the device and out keeps its bytes
+    for k, field, val in ((5, "rb", len(w["ref"])), (3, "h0", 0), (9, "read", 10**6)):
+        b = w["seeds"].copy()
+        b[k][field] = val
+        dev = bsw.seeds_to_device(w["reads"], w["read_off"], w["ref"], b)
+        out = torch.full((len(b) * 32,), 0x5a, dtype=torch.uint8, device="cuda")
+        with pytest.raises(bsw.BswError) as ei:
+            ctx.extend_seeds_device(dev, w["scoring"], out)
+        assert ei.value.code == bsw.EINVAL and f"seed {k}" in str(ei.value), str(ei.value)
+        assert bool((out == 0x5a).all())
+    # a code > 4 in the reads
+    reads = w["reads"].copy()
+    reads[1000] = 9
+    dev = bsw.seeds_to_device(reads, w["read_off"], w["ref"], w["seeds"])
+    out = torch.full((len(w["seeds"]) * 32,), 0x5a, dtype=torch.uint8, device="cuda")
+    with pytest.raises(bsw.BswError) as ei:
+        ctx.extend_seeds_device(dev, w["scoring"], out)
+    assert "read byte" in str(ei.value)
+    assert bool((out == 0x5a).all())
+    # the context still works afterwards
+    got = ctx.extend_seeds(w["reads"], w["read_off"], w["ref"], w["seeds"], w["scoring"])
+    assert len(got) == len(w["seeds"])
+
+
+def test_bench_size_sampled(bsw, ctx, oracle_lib):
+    """The workload the benchmark times, in its launch configuration (device
+    form with a reversed reference), checked on a seeded sample of seeds."""
+    w = synth.seed_workload(**synth.SEED_BENCH)
+    got = run_device(bsw, ctx, w, with_rev=True)
+    idx = np.sort(np.random.default_rng(17).choice(len(w["seeds"]), 3000, replace=False))
+    assert_same(got[idx], reference(w, seeds=w["seeds"][idx]), "sample")

@@ -130,3 +130,45 @@ def test_left_extension_is_bsw_on_the_reversed_prefix(seeds_mod, oracle_lib):
         assert (o["qbeg"], o["rbeg"]) == (0, rb - res["gtle"])
     else:
         assert (o["qbeg"], o["rbeg"]) == (qb - res["qle"], rb - res["tle"])
+
+
+def test_synthetic_seeds_are_exact_diagonal_matches():
+    """The generator's seeds are what the driver assumes: read[qb, qe)
+    equals ref[rb, rb + qe - qb), with no N, and at least 19 bases."""
+    w = synth.seed_workload(400, seed=21)
+    s = w["seeds"]
+    assert len(s) > 400
+    for x in s:
+        r0 = int(w["read_off"][x["read"]])
+        a = w["reads"][r0 + x["qb"]:r0 + x["qe"]]
+        b = w["ref"][x["rb"]:x["rb"] + x["qe"] - x["qb"]]
+        assert np.array_equal(a, b) and (a < 4).all() and x["qe"] - x["qb"] >= 19
+        assert x["h0"] == x["qe"] - x["qb"]
+
+
+def test_reference_invariants_on_synthetic_reads(seeds_mod):
+    """Properties every record has by definition: the extended intervals
+    contain the seed; a side with nothing to extend keeps the seed boundary
+    and the score; a side that kept the read end reaches it; the reference
+    interval stays inside the reference."""
+    w = synth.seed_workload(1500, seed=22, ref_len=300_000)
+    s, o = w["seeds"], seeds_mod.extend_seeds(w["reads"], w["read_off"], w["ref"],
+                                              w["seeds"], synth.BWA_DEFAULT)
+    L = (w["read_off"][s["read"] + 1] - w["read_off"][s["read"]]).astype(np.int64)
+    re = s["rb"] + s["qe"] - s["qb"]
+    assert (o["qbeg"] <= s["qb"]).all() and (o["qend"] >= s["qe"]).all()
+    assert (o["rbeg"] <= s["rb"]).all() and (o["rend"] >= re).all()
+    assert (o["rbeg"] >= 0).all() and (o["rend"] <= len(w["ref"])).all()
+    left, right = o["how"] & 3, o["how"] >> 2
+    assert ((left == seeds_mod.NONE) == (s["qb"] == 0)).all()
+    assert ((right == seeds_mod.NONE) == (s["qe"] == L)).all()
+    assert (o["qbeg"][left == seeds_mod.READ_END] == 0).all()
+    assert (o["qend"][right == seeds_mod.READ_END] == L[right == seeds_mod.READ_END]).all()
+    both = (left == seeds_mod.NONE) & (right == seeds_mod.NONE)
+    assert (o["score"][both] == s["h0"][both]).all()
+    # a read-end choice never gives up more than the bonus less one
+    # (score, per side, is at least the side's best - (bonus - 1) >= h0 - 4)
+    assert (o["score"] >= s["h0"] - 8).all()
+    # every choice occurs on read-shaped data
+    for side in (left, right):
+        assert {0, 1, 2} <= set(np.unique(side).tolist())
