@@ -139,7 +139,7 @@ def serve(bsw, synth, batch, host, capacity, rho, n_requests, seed=3):
             "gcups": round(st["gcups"], 2), "window_s": round(st["window_s"], 3)}
 
 
-def seed_driver(bsw, synth, torch, np, tune_cache, steps, warmup):
+def seed_driver(bsw, synth, torch, np, tune_cache, steps, warmup, tune=True):
     """Read-level seed extension (left, end choice, right) over the seed
     benchmark workload, device-resident, reversed reference supplied."""
     t0 = time.time()
@@ -150,6 +150,12 @@ def seed_driver(bsw, synth, torch, np, tune_cache, steps, warmup):
                               with_ref_rev=True)
     out = torch.empty(ns * bsw.SEED_RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     ctx = bsw.Context(tune_cache=tune_cache)
+    tuned = None
+    if tune:
+        # the seed driver's own launch shape (untimed)
+        ms, tuned = ctx.tune_seeds(dev, sw["scoring"], out, reps=3)
+        tuned["tune_best_ms"] = round(ms, 3)
+        log(f"seed driver tuned: {tuned}")
     for _ in range(max(1, warmup)):
         ctx.extend_seeds_device(dev, sw["scoring"], out)
     cells = ctx.last_cells()
@@ -173,7 +179,7 @@ def seed_driver(bsw, synth, torch, np, tune_cache, steps, warmup):
                        f"{len(sw['ref'])}-base random reference, 1-5% substitutions, "
                        f"0.1-1% indels, 1% N; {ns} seeds (exact runs >= 19 bp, <= 3 per "
                        "read); BWA default scoring; reversed reference supplied",
-           "seeds": ns, "reads": nr, "cells": int(cells)}
+           "seeds": ns, "reads": nr, "cells": int(cells), "tuned": tuned}
     return leg, sw
 
 
@@ -288,7 +294,7 @@ def main():
     seeds_leg = None
     if not args.no_seeds:
         seeds_leg, sw = seed_driver(bsw, synth, torch, np, tune_cache, args.steps,
-                                    args.warmup)
+                                    args.warmup, tune=not args.no_tune)
         log(f"seed driver: {seeds_leg}")
 
     # dominant kernel: the DP launch with the largest device time; its

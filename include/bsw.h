@@ -108,7 +108,8 @@ typedef struct bsw_ctx_opts {
   size_t  hbm_budget;      /* cap on the context's device arena in bytes
                             * (0 = none); a call that would need more fails
                             * with BSW_ETOOBIG before any work is enqueued   */
-  const char* tune_cache;  /* JSON file of tuned launch shapes, or NULL: an
+  const char* tune_cache;  /* JSON file of tuned launch shapes (the path is
+                            * copied at creation), or NULL: an
                             * entry for the device, band limit, gap symmetry
                             * and min_lane_bits of a call is used when
                             * present; bsw_ctx_tune adds or replaces it      */
@@ -355,6 +356,19 @@ int bsw_extend_seeds_device(bsw_ctx* ctx, const uint8_t* reads, uint64_t reads_l
                             const uint8_t* ref, const uint8_t* ref_rev, uint64_t ref_len,
                             const bsw_seed* seeds, int64_t n, const bsw_params* params,
                             bsw_seed_result* out, void* stream, int32_t async);
+
+/* Autotuner of the seed driver: as bsw_ctx_tune, with whole seed calls
+ * (arguments as bsw_extend_seeds_device, blocking, on the context's
+ * stream) as the unit that is timed.  The winner is the launch shape of
+ * both BSW passes of every later seed call of the context (pair batches
+ * keep their own), stored in tune_cache under its own entry.  out3
+ * (nullable) receives it as bsw_ctx_tune_info describes. */
+int bsw_ctx_tune_seeds(bsw_ctx* ctx, const uint8_t* reads, uint64_t reads_len,
+                       const uint64_t* read_off, int64_t n_reads,
+                       const uint8_t* ref, const uint8_t* ref_rev, uint64_t ref_len,
+                       const bsw_seed* seeds, int64_t n, const bsw_params* params,
+                       bsw_seed_result* out, int32_t reps, double* best_ms,
+                       int32_t out3[3]);
 
 /* Text of the calling thread's most recent error ("" if none). */
 const char* bsw_last_error(void);

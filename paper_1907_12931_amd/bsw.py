@@ -126,6 +126,11 @@ def lib():
         L.bsw_extend_seeds_device.argtypes = [
             _VP, _VP, ctypes.c_uint64, _VP, ctypes.c_int64, _VP, _VP, ctypes.c_uint64,
             _VP, ctypes.c_int64, ctypes.POINTER(Params), _VP, _VP, ctypes.c_int32]
+        L.bsw_ctx_tune_seeds.restype = ctypes.c_int
+        L.bsw_ctx_tune_seeds.argtypes = [
+            _VP, _VP, ctypes.c_uint64, _VP, ctypes.c_int64, _VP, _VP, ctypes.c_uint64,
+            _VP, ctypes.c_int64, ctypes.POINTER(Params), _VP, ctypes.c_int32,
+            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
         L.bsw_ctx_tune_info.restype = ctypes.c_int
         L.bsw_ctx_tune_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
         L.bsw_server_create.restype = ctypes.c_int
@@ -175,8 +180,9 @@ class Context:
 
     def __init__(self, device=0, min_lane_bits=0, path=PATH_BATCHED,
                  hbm_budget=0, tune_cache=None, graph=True):
-        o = CtxOpts(device, min_lane_bits, 0, path, hbm_budget,
-                    tune_cache.encode() if tune_cache else None, 0 if graph else 1)
+        # the library copies the path; the bytes only need to live for the call
+        tc = tune_cache.encode() if tune_cache else None
+        o = CtxOpts(device, min_lane_bits, 0, path, hbm_budget, tc, 0 if graph else 1)
         h = _VP()
         _check(lib().bsw_ctx_create(ctypes.byref(h), ctypes.byref(o)))
         self._h = h
@@ -262,6 +268,22 @@ class Context:
             dev["ref"].data_ptr(), rev.data_ptr() if rev is not None else None,
             dev["ref"].numel(), dev["seeds"].data_ptr(), n, params, out.data_ptr(), s,
             1 if async_ else 0))
+
+    def tune_seeds(self, dev, scoring, out, reps=2):
+        """Autotune the seed driver's launch shape on a device seed workload
+        (as for ``extend_seeds_device``); returns (best_ms, shape dict)."""
+        n = dev["seeds"].numel() // SEED_DTYPE.itemsize
+        params = make_params([scoring])
+        rev = dev.get("ref_rev")
+        ms = ctypes.c_double(0)
+        v = (ctypes.c_int32 * 3)()
+        _check(lib().bsw_ctx_tune_seeds(
+            self._h, dev["reads"].data_ptr(), dev["reads"].numel(),
+            dev["read_off"].data_ptr(), dev["read_off"].numel() - 1,
+            dev["ref"].data_ptr(), rev.data_ptr() if rev is not None else None,
+            dev["ref"].numel(), dev["seeds"].data_ptr(), n, params, out.data_ptr(), reps,
+            ctypes.byref(ms), v))
+        return ms.value, {"side_streams": v[0], "occ8_pct": v[1], "spec16": v[2]}
 
     def last_cells(self):
         """Band cells settled by the last completed call (all its passes)."""

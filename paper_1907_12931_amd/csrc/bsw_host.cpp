@@ -160,16 +160,6 @@ KParams to_kparams(const bsw_params& p) {
 }
 
 
-// Launch shapes of the batched path that the tuner chooses.
-struct Tune {
-  int nside = 4;    // side streams the classes are spread over (1, 2 or 4)
-  int occ8 = 100;   // percent of the resident groups per CU for 8-bit classes
-  int spec16 = 1;   // try pairs whose bound needs 16 bits at 8 bits first
-  bool operator==(const Tune& o) const {
-    return nside == o.nside && occ8 == o.occ8 && spec16 == o.spec16;
-  }
-};
-
 // What a captured batched pipeline depends on besides the scoring values.
 struct GraphKey {
   Args a;
@@ -242,9 +232,12 @@ struct bsw_ctx {
   int n_graph_launch = 0;
   // launch shapes of the batched path (defaults, a cache entry or
   // bsw_ctx_tune's choice)
-  Tune tune;
+  // (per workload kind: pair batches, and the seed driver's two passes)
+  Tune tunes[NKIND];
+  int kind = KIND_PAIRS;  // kind of the call being enqueued
   char dev_name[64] = {0};
-  std::string tune_key;  // cache entry the current shapes came from
+  std::string tune_keys[NKIND];  // cache entry each kind's shape came from
+  std::string tune_cache;  // copy of opts.tune_cache (which points here)
 };
 
 namespace {
@@ -309,7 +302,7 @@ void enqueue_prep_bin(bsw_ctx* c, const Args& a, const Work& w, hipStream_t s) {
   const uint64_t* qe = a.q_end ? a.q_end : a.q_off + 1;
   const uint64_t* te = a.t_end ? a.t_end : a.t_off + 1;
   launch_prep(a.n, a.q, a.t, a.q_off, qe, a.t_off, te, a.h0, a.pid, a.n_params, c->d_kp,
-              c->opts.min_lane_bits, c->tune.spec16, w.keys, w.hist, w.st, s);
+              c->opts.min_lane_bits, c->tunes[c->kind].spec16, w.keys, w.hist, w.st, s);
   if (!a.codes_checked) {
     launch_codes(a.q, a.q_off, a.n, w.st, 0, s);
     launch_codes(a.t, a.t_off, a.n, w.st, 0, s);
@@ -336,7 +329,7 @@ int end_launch(bsw_ctx* c, hipStream_t ls) {
 // classes by the tuned share
 int tuned_per_cu(const bsw_ctx* c, int cls, int fit) {
   if (cls >= CLS_W16) return fit;
-  const int t = fit * c->tune.occ8 / 100;
+  const int t = fit * c->tunes[c->kind].occ8 / 100;
   return t < 1 ? 1 : t;
 }
 
@@ -388,7 +381,7 @@ int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan&
   if (ev) HIPCHK(hipEventRecord(c->ev[2], s));
   c->n_launch = 0;
   HIPCHK(hipEventRecord(c->fork_ev, s));
-  const int nside = c->tune.nside;
+  const int nside = c->tunes[c->kind].nside;
   for (int k = 0; k < nside; ++k) HIPCHK(hipStreamWaitEvent(c->side[k], c->fork_ev, 0));
   int order[NCLS], no = 0;
   for (int cls = CLS_W16 - 1; cls >= CLS_L8; --cls) order[no++] = cls;
@@ -426,10 +419,10 @@ int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan&
 // Tuned shapes are cached per device, band limit, gap symmetry and lane
 // width floor in a small JSON file, one entry per line:
 //   "gfx950:cu256:w100:sym1:mb0": {"nside": 4, "occ8": 100, "spec16": 1, "ms": 57.1},
-std::string tune_key(const bsw_ctx* c, int wmax, bool sym) {
+std::string tune_key(const bsw_ctx* c, int wmax, bool sym, int kind) {
   char k[160];
-  std::snprintf(k, sizeof k, "%s:cu%d:w%d:sym%d:mb%d", c->dev_name, c->num_cu, wmax,
-                sym ? 1 : 0, c->opts.min_lane_bits);
+  std::snprintf(k, sizeof k, "%s:cu%d:w%d:sym%d:mb%d%s", c->dev_name, c->num_cu, wmax,
+                sym ? 1 : 0, c->opts.min_lane_bits, kind == KIND_SEEDS ? ":seeds" : "");
   return k;
 }
 
@@ -457,7 +450,7 @@ bool cache_lookup(const char* path, const std::string& key, Tune* t) {
     if (std::sscanf(kv.second.c_str(), "{\"nside\": %d, \"occ8\": %d, \"spec16\": %d, \"ms\": %lf}",
                     &x.nside, &x.occ8, &x.spec16, &ms) != 4)
       return false;
-    if ((x.nside != 1 && x.nside != 2 && x.nside != 4) || x.occ8 < 1 || x.occ8 > 100 ||
+    if (x.nside < 1 || x.nside > bsw_ctx::NSIDE || x.occ8 < 1 || x.occ8 > 100 ||
         (x.spec16 != 0 && x.spec16 != 1))
       return false;
     *t = x;
@@ -495,11 +488,11 @@ int cache_store(const char* path, const std::string& key, const Tune& t, double 
 // Shapes for this call's scoring: from the cache when it has an entry.
 void pick_tune(bsw_ctx* c, int wmax, bool sym) {
   if (!c->opts.tune_cache) return;
-  const std::string key = tune_key(c, wmax, sym);
-  if (key == c->tune_key) return;
-  c->tune_key = key;
+  const std::string key = tune_key(c, wmax, sym, c->kind);
+  if (key == c->tune_keys[c->kind]) return;
+  c->tune_keys[c->kind] = key;
   Tune t;
-  if (cache_lookup(c->opts.tune_cache, key, &t)) c->tune = t;
+  if (cache_lookup(c->opts.tune_cache, key, &t)) c->tunes[c->kind] = t;
 }
 
 // Batched path: plan, make sure every buffer exists, then run the steps
@@ -532,7 +525,7 @@ int run_batched(bsw_ctx* c, const Args& a, hipStream_t s) {
   key.lb = c->longbuf.p;
   key.wmax = wmax;
   key.sym = sym;
-  key.tune = c->tune;
+  key.tune = c->tunes[c->kind];
   if (!c->gexec || !same_key(key, c->gkey)) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
@@ -559,6 +552,53 @@ int run_batched(bsw_ctx* c, const Args& a, hipStream_t s) {
   HIPCHK(hipEventRecord(c->ev[0], s));
   HIPCHK(hipGraphLaunch(c->gexec, s));
   HIPCHK(hipEventRecord(c->ev[3], s));
+  return BSW_OK;
+}
+
+// The tuning loop (see ctx_tune_shapes).  The kind's cache key is set
+// first, so that the calls leave the candidate shapes alone.
+int tune_shapes(bsw_ctx* c, int kind, int n_params, int reps, int (*run)(bsw_ctx*, void*),
+                void* arg, double* best_ms) {
+  int wmax;
+  bool sym;
+  scan_params(c, n_params, &wmax, &sym);
+  const std::string key = tune_key(c, wmax, sym, kind);
+  c->tune_keys[kind] = key;
+  // the default shape first: another shape must beat it by more than 1%
+  std::vector<Tune> cands(1);
+  for (int ns : {4, 2, 1})
+    for (int occ : {100, 50})
+      for (int sp : {1, 0}) {
+        Tune x;
+        x.nside = ns;
+        x.occ8 = occ;
+        x.spec16 = sp;
+        if (!(x == cands[0])) cands.push_back(x);
+      }
+  Tune best = c->tunes[kind];
+  double best_t = 1e300;
+  std::vector<double> ts;
+  int rc = BSW_OK;
+  for (const Tune& x : cands) {
+    c->tunes[kind] = x;
+    ts.clear();
+    for (int r = 0; r <= reps && rc == BSW_OK; ++r) {
+      rc = run(c, arg);
+      if (rc == BSW_OK && r > 0) ts.push_back(c->timing[0]);
+    }
+    if (rc) break;
+    std::sort(ts.begin(), ts.end());
+    const double med = ts[ts.size() / 2];
+    if (med < best_t * (best_t < 1e300 ? 0.99 : 1.0)) {
+      best_t = med;
+      best = x;
+    }
+  }
+  c->tunes[kind] = best;
+  if (rc) return rc;
+  if (best_ms) *best_ms = best_t;
+  if (c->opts.tune_cache && (rc = cache_store(c->opts.tune_cache, key, best, best_t)))
+    return rc;
   return BSW_OK;
 }
 
@@ -766,6 +806,19 @@ void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*)) {
 
 SeedState*& ctx_seed_state(bsw_ctx* c) { return c->seed; }
 
+void ctx_set_kind(bsw_ctx* c, int kind) { c->kind = kind; }
+
+int ctx_tune_shapes(bsw_ctx* c, int kind, int n_params, int reps,
+                    int (*run)(bsw_ctx*, void*), void* arg, double* best_ms) {
+  const int saved = c->kind;
+  c->kind = kind;
+  const int rc = tune_shapes(c, kind, n_params, reps, run, arg, best_ms);
+  c->kind = saved;
+  return rc;
+}
+
+Tune ctx_shape(const bsw_ctx* c, int kind) { return c->tunes[kind]; }
+
 unsigned long long ctx_last_cells(const bsw_ctx* c) {
   unsigned long long sum = 0;
   for (int k = 0; k <= NCLS; ++k) sum += c->h_status->cls_cells[k];
@@ -806,6 +859,10 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
   bsw_ctx* c = new (std::nothrow) bsw_ctx;
   if (!c) return fail(BSW_ENOMEM, "out of host memory");
   c->opts = o;
+  if (o.tune_cache) {
+    c->tune_cache = o.tune_cache;
+    c->opts.tune_cache = c->tune_cache.c_str();
+  }
   c->device = o.device;
   c->num_cu = prop.multiProcessorCount;
   std::snprintf(c->dev_name, sizeof c->dev_name, "%s", prop.gcnArchName);
@@ -925,62 +982,28 @@ int bsw_ctx_tune(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
     return fail(BSW_EINVAL, "a required device pointer is NULL");
   if ((rc = set_device(c))) return rc;
   for (int i = 0; i < n_params; ++i) c->h_kp[i] = to_kparams(params[i]);
-  int wmax;
-  bool sym;
-  scan_params(c, n_params, &wmax, &sym);
-  const Args a = {n, q, q_off, t, t_off, h0, param_id, n_params, out, nullptr,
-                  nullptr, nullptr, false};
-  // the default shape first: another shape must beat it by more than 1%
-  std::vector<Tune> cands(1);
-  for (int ns : {4, 2, 1})
-    for (int occ : {100, 50})
-      for (int sp : {1, 0}) {
-        Tune x;
-        x.nside = ns;
-        x.occ8 = occ;
-        x.spec16 = sp;
-        if (!(x == cands[0])) cands.push_back(x);
-      }
-  // every candidate runs eagerly: one warm-up call, then reps timed calls;
-  // the score is their median device time, first to last step
+  Args a = {n, q, q_off, t, t_off, h0, param_id, n_params, out, nullptr,
+            nullptr, nullptr, false};
+  // every candidate runs eagerly, one whole call at a time
+  auto run = [](bsw_ctx* cc, void* arg) {
+    int r = run_pipeline(cc, *(const Args*)arg, cc->stream);
+    if (r == BSW_OK && hipStreamSynchronize(cc->stream) != hipSuccess)
+      r = fail(BSW_EDEVICE, "stream synchronisation failed");
+    return r == BSW_OK ? finish_call(cc) : r;
+  };
   const int32_t saved = c->opts.no_graph;
   c->opts.no_graph = 1;
-  Tune best = c->tune;
-  double best_t = 1e300;
-  std::vector<double> ts;
-  for (const Tune& x : cands) {
-    c->tune = x;
-    ts.clear();
-    for (int r = 0; r <= reps && rc == BSW_OK; ++r) {
-      rc = run_pipeline(c, a, c->stream);
-      if (rc == BSW_OK && hipStreamSynchronize(c->stream) != hipSuccess)
-        rc = fail(BSW_EDEVICE, "stream synchronisation failed");
-      if (rc == BSW_OK) rc = finish_call(c);
-      if (rc == BSW_OK && r > 0) ts.push_back(c->timing[0]);
-    }
-    if (rc) break;
-    std::sort(ts.begin(), ts.end());
-    const double med = ts[ts.size() / 2];
-    if (med < best_t * (best_t < 1e300 ? 0.99 : 1.0)) {
-      best_t = med;
-      best = x;
-    }
-  }
+  c->kind = KIND_PAIRS;
+  rc = tune_shapes(c, KIND_PAIRS, n_params, reps, run, &a, best_ms);
   c->opts.no_graph = saved;
-  if (rc) return rc;
-  c->tune = best;
-  c->tune_key = tune_key(c, wmax, sym);
-  if (best_ms) *best_ms = best_t;
-  if (c->opts.tune_cache && (rc = cache_store(c->opts.tune_cache, c->tune_key, best, best_t)))
-    return rc;
-  return BSW_OK;
+  return rc;
 }
 
 int bsw_ctx_tune_info(bsw_ctx* c, int32_t out3[3]) {
   if (!c || !out3) return fail(BSW_EINVAL, "NULL argument");
-  out3[0] = c->tune.nside;
-  out3[1] = c->tune.occ8;
-  out3[2] = c->tune.spec16;
+  out3[0] = c->tunes[KIND_PAIRS].nside;
+  out3[1] = c->tunes[KIND_PAIRS].occ8;
+  out3[2] = c->tunes[KIND_PAIRS].spec16;
   return BSW_OK;
 }
 

@@ -144,6 +144,36 @@ __device__ int diagonal_rows(const uint8_t* qs, const uint8_t* ts, int L, int h0
   return 0x7fffffff;  // the walk never stops: no estimate
 }
 
+// Add one to cnt[key] for every lane with active set, with one atomic per
+// distinct key in the wave (pairs that share a bin, as short or empty
+// queries of one length do, would otherwise serialise on its counter).
+// The lanes are grouped by key first (ALU only); then the first lane of
+// each group adds the group's size, all groups in one atomic instruction.
+// Returns the lane's slot: the counter's old value plus the lane's rank in
+// its group.  Every lane of the wave must call it.
+__device__ __forceinline__ uint32_t wave_count_add(uint32_t* cnt, uint32_t key,
+                                                   bool active) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned long long todo = __ballot(active);
+  int leader = lane;
+  uint32_t rank = 0, size = 0;
+  while (todo) {
+    const int l = __builtin_ctzll(todo);
+    const uint32_t kl = (uint32_t)__builtin_amdgcn_readlane((int)key, l);
+    const unsigned long long same = __ballot(active && key == kl);
+    todo &= ~same;
+    if ((same >> lane) & 1ull) {
+      leader = l;
+      rank = (uint32_t)__popcll(same & below);
+      size = (uint32_t)__popcll(same);
+    }
+  }
+  uint32_t base = 0;
+  if (active && leader == lane) base = atomicAdd(&cnt[key], size);
+  return (uint32_t)__shfl((int)base, leader, 64) + rank;
+}
+
 // Pair k's sequences are q[q_off[k] .. q_end[k]) and t[t_off[k] .. t_end[k]);
 // for an ordinary batch q_end = q_off + 1 and t_end = t_off + 1.  Each wave
 // takes 64 consecutive pairs, one per lane.
@@ -194,40 +224,42 @@ k_prep(int64_t n, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
       const int r = diagonal_rows(q + wq, t + wt, wl, wh, kp[wp]);
       if (lane == l) rows_est = imin(rows_est, r);
     }
-    if (!ok) continue;
-    // bound on every stored H and E of the pair (Sec. 5.4.1 precision)
-    const int64_t U = (int64_t)hh + (int64_t)P.amax * (ql < tl ? ql : tl);
-    int wd = U <= 255 ? W8 : (U <= 65535 ? W16 : W32);
-    if (min_bits >= 16 && wd < W16) wd = W16;
-    if (min_bits >= 32) wd = W32;
-    // 16-bit pairs start at 8 bits when the seed itself leaves room
-    const int slack = P.amax - P.oe_del > 0 ? P.amax - P.oe_del : 0;
-    const bool spec8 =
-        wd == W8 || (spec16 && wd == W16 && min_bits < 16 && hh + slack <= 255);
-    int cls, cap;
-    if (ql > 256) {
-      cls = CLS_LONG;
-      cap = BSW_MAX_LEN;
-      atomicMax(&st->long_max, (unsigned long long)ql);
-    } else if (spec8) {
-      int c = 0;
-      while (L8_CAP[c] < ql) ++c;
-      cls = CLS_L8 + c;
-      cap = L8_CAP[c];
-    } else {
-      int c = 0;
-      while (LW_CAP[c] < ql) ++c;
-      cls = (wd == W16 ? CLS_W16 : CLS_W32) + c;
-      cap = LW_CAP[c];
+    uint32_t key = 0;
+    if (ok) {
+      // bound on every stored H and E of the pair (Sec. 5.4.1 precision)
+      const int64_t U = (int64_t)hh + (int64_t)P.amax * (ql < tl ? ql : tl);
+      int wd = U <= 255 ? W8 : (U <= 65535 ? W16 : W32);
+      if (min_bits >= 16 && wd < W16) wd = W16;
+      if (min_bits >= 32) wd = W32;
+      // 16-bit pairs start at 8 bits when the seed itself leaves room
+      const int slack = P.amax - P.oe_del > 0 ? P.amax - P.oe_del : 0;
+      const bool spec8 =
+          wd == W8 || (spec16 && wd == W16 && min_bits < 16 && hh + slack <= 255);
+      int cls, cap;
+      if (ql > 256) {
+        cls = CLS_LONG;
+        cap = BSW_MAX_LEN;
+        atomicMax(&st->long_max, (unsigned long long)ql);
+      } else if (spec8) {
+        int c = 0;
+        while (L8_CAP[c] < ql) ++c;
+        cls = CLS_L8 + c;
+        cap = L8_CAP[c];
+      } else {
+        int c = 0;
+        while (LW_CAP[c] < ql) ++c;
+        cls = (wd == W16 ? CLS_W16 : CLS_W32) + c;
+        cap = LW_CAP[c];
+      }
+      int qq = (int)((int64_t)ql * 64 / (cap + 1));
+      int tq = rows_est >> 4;
+      qq = qq > 63 ? 63 : qq;
+      tq = tq > 63 ? 63 : (tq < 0 ? 0 : tq);
+      const uint32_t sub = ((uint32_t)(63 - qq) << 6) | (uint32_t)(63 - tq);
+      key = ((uint32_t)cls << KEY_SUB_BITS) | sub;
+      keys[k] = key;
     }
-    int qq = (int)((int64_t)ql * 64 / (cap + 1));
-    int tq = rows_est >> 4;
-    qq = qq > 63 ? 63 : qq;
-    tq = tq > 63 ? 63 : (tq < 0 ? 0 : tq);
-    const uint32_t sub = ((uint32_t)(63 - qq) << 6) | (uint32_t)(63 - tq);
-    const uint32_t key = ((uint32_t)cls << KEY_SUB_BITS) | sub;
-    keys[k] = key;
-    atomicAdd(&hist[key], 1u);
+    (void)wave_count_add(hist, key, ok);
   }
 }
 
@@ -324,10 +356,15 @@ __global__ void k_scatter(int64_t n, const uint64_t* __restrict__ q_off,
                           uint32_t* __restrict__ cursor,
                           PairDesc* __restrict__ desc, const Status* st) {
   if (st->bad) return;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t key = keys[k];
-    const uint32_t pos = atomicAdd(&cursor[key], 1u);
+  // the loop bound is uniform per block, so every lane of a wave takes part
+  // in each slot grab
+  for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < n;
+       k0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = k0 + threadIdx.x;
+    const bool active = k < n;
+    const uint32_t key = active ? keys[k] : 0u;
+    const uint32_t pos = wave_count_add(cursor, key, active);
+    if (!active) continue;
     PairDesc d;
     d.qo = q_off[k];
     d.to = t_off[k];

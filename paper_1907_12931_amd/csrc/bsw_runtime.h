@@ -29,6 +29,20 @@ struct Args {
   bool codes_checked;  // the sequence bytes were validated beforehand
 };
 
+// Launch shapes of the batched path that the tuner chooses.
+struct Tune {
+  int nside = 4;    // side streams the classes are spread over (1..4)
+  int occ8 = 100;   // percent of the resident groups per CU for 8-bit classes
+  int spec16 = 1;   // try pairs whose bound needs 16 bits at 8 bits first
+  bool operator==(const Tune& o) const {
+    return nside == o.nside && occ8 == o.occ8 && spec16 == o.spec16;
+  }
+};
+
+// Workload kinds with a shape of their own: pair batches, and the BSW
+// passes of the read-level seed driver (many short, similar pairs).
+enum { KIND_PAIRS = 0, KIND_SEEDS = 1, NKIND = 2 };
+
 // Set the calling thread's error text; returns code.
 int set_error(int code, const char* fmt, ...);
 
@@ -99,6 +113,19 @@ int ctx_set_device(bsw_ctx* c);
 // Mark the context as having an asynchronous call in flight on s whose
 // completion is checked by done (bsw_ctx_wait calls it).
 void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*));
+
+// Kind of the calls enqueued from now on (the shape they use and the tune
+// cache entry it comes from).
+void ctx_set_kind(bsw_ctx* c, int kind);
+// Autotune the shape of one kind: for every candidate, run(c, arg) makes
+// one whole blocking call (reps + 1 times, the first untimed); the score is
+// the median of the calls' device time (bsw_ctx_last_timing [0]); another
+// shape must beat the default by more than 1%.  The winner becomes the
+// kind's shape and is stored in the tune cache.  n_params: size of the
+// loaded scoring table.
+int ctx_tune_shapes(bsw_ctx* c, int kind, int n_params, int reps,
+                    int (*run)(bsw_ctx*, void*), void* arg, double* best_ms);
+Tune ctx_shape(const bsw_ctx* c, int kind);
 
 // State of the read-level seed driver, owned by the context (created on
 // first use, released with the context).

@@ -112,9 +112,17 @@ struct SeedArgs {
   bsw_seed_result* out;
 };
 
+// Both BSW passes of a seed call use the context's seed-driver shape.
+struct SeedKind {
+  bsw_ctx* c;
+  explicit SeedKind(bsw_ctx* cc) : c(cc) { ctx_set_kind(c, KIND_SEEDS); }
+  ~SeedKind() { ctx_set_kind(c, KIND_PAIRS); }
+};
+
 // Enqueue one seed call on stream s (n >= 1; params already loaded).
 int seeds_enqueue(bsw_ctx* c, SeedState* S, const SeedArgs& a, const bsw_params& P,
                   hipStream_t s) {
+  const SeedKind kind(c);
   const SeedLayout L = seed_layout(a.n);
   const size_t rr = align_up(a.reads_len + 1, 256);
   int rc;
@@ -202,15 +210,11 @@ int seed_done(bsw_ctx* c) {
   return BSW_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int bsw_extend_seeds_device(bsw_ctx* c, const uint8_t* reads, uint64_t reads_len,
-                            const uint64_t* read_off, int64_t n_reads, const uint8_t* ref,
-                            const uint8_t* ref_rev, uint64_t ref_len, const bsw_seed* seeds,
-                            int64_t n, const bsw_params* params, bsw_seed_result* out,
-                            void* stream, int32_t async) {
+// Checks of the device form's host-side arguments.
+int check_device_args(bsw_ctx* c, const uint8_t* reads, uint64_t reads_len,
+                      const uint64_t* read_off, int64_t n_reads, const uint8_t* ref,
+                      uint64_t ref_len, const bsw_seed* seeds, int64_t n,
+                      const bsw_seed_result* out) {
   if (!c) return set_error(BSW_EINVAL, "ctx is NULL");
   if (n < 0 || n > 0x7fffffffLL)
     return set_error(BSW_EINVAL, "n = %lld out of range", (long long)n);
@@ -221,7 +225,64 @@ int bsw_extend_seeds_device(bsw_ctx* c, const uint8_t* reads, uint64_t reads_len
     return set_error(BSW_EINVAL, "a required device pointer is NULL");
   if (reads_len > (1ull << 48) || ref_len > (1ull << 48))
     return set_error(BSW_EINVAL, "reads_len or ref_len above 2^48");
-  int rc = ctx_set_params(c, params, 1);
+  return BSW_OK;
+}
+
+struct TuneRun {
+  SeedState* S;
+  SeedArgs a;
+  bsw_params P;
+};
+
+// One whole blocking seed call (the tuner's unit of work).
+int tune_run(bsw_ctx* c, void* arg) {
+  const TuneRun& r = *(const TuneRun*)arg;
+  const hipStream_t s = ctx_stream(c);
+  int rc = seeds_enqueue(c, r.S, r.a, r.P, s);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(s));
+  return seed_done(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int bsw_ctx_tune_seeds(bsw_ctx* c, const uint8_t* reads, uint64_t reads_len,
+                       const uint64_t* read_off, int64_t n_reads, const uint8_t* ref,
+                       const uint8_t* ref_rev, uint64_t ref_len, const bsw_seed* seeds,
+                       int64_t n, const bsw_params* params, bsw_seed_result* out,
+                       int32_t reps, double* best_ms, int32_t out3[3]) {
+  int rc = check_device_args(c, reads, reads_len, read_off, n_reads, ref, ref_len, seeds, n,
+                             out);
+  if (rc) return rc;
+  if (n < 1) return set_error(BSW_EINVAL, "tuning needs at least one seed");
+  if (reps < 1 || reps > 100) return set_error(BSW_EINVAL, "reps must be 1..100");
+  if ((rc = ctx_set_params(c, params, 1))) return rc;
+  if ((rc = ctx_set_device(c))) return rc;
+  TuneRun r;
+  if ((rc = seed_state(c, &r.S))) return rc;
+  r.a = {reads, reads_len, read_off, n_reads, ref, ref_rev, ref_len, seeds, n, out};
+  r.P = *params;
+  if ((rc = ctx_tune_shapes(c, KIND_SEEDS, 1, reps, tune_run, &r, best_ms))) return rc;
+  if (out3) {
+    const Tune t = ctx_shape(c, KIND_SEEDS);
+    out3[0] = t.nside;
+    out3[1] = t.occ8;
+    out3[2] = t.spec16;
+  }
+  return BSW_OK;
+}
+
+int bsw_extend_seeds_device(bsw_ctx* c, const uint8_t* reads, uint64_t reads_len,
+                            const uint64_t* read_off, int64_t n_reads, const uint8_t* ref,
+                            const uint8_t* ref_rev, uint64_t ref_len, const bsw_seed* seeds,
+                            int64_t n, const bsw_params* params, bsw_seed_result* out,
+                            void* stream, int32_t async) {
+  int rc = check_device_args(c, reads, reads_len, read_off, n_reads, ref, ref_len, seeds, n,
+                             out);
+  if (rc || n == 0) return rc;
+  rc = ctx_set_params(c, params, 1);
   if (rc) return rc;
   if ((rc = ctx_set_device(c))) return rc;
   SeedState* S;

@@ -113,7 +113,11 @@ def test_autotuner_keeps_results_and_caches_its_choice(oracle_lib, bsw, tmp_path
     out, _ = bsw.alloc_outputs(len(b["h0"]))
     cache = str(tmp_path / "tune.json")
     c = bsw.Context(tune_cache=cache)
+    # the context holds its own copy of the path: reuse the memory of the
+    # binding's temporary string before the cache is written
+    junk = [bytes([0x41 + i % 20]) * (len(cache) + 1) for i in range(20000)]
     ms, shape = c.tune(dev, b["scorings"], out, reps=1)
+    del junk
     assert ms > 0 and shape["side_streams"] in (1, 2, 4)
     _same(bsw.outputs_to_numpy(out), want, "tune call")
     out.fill_(0)

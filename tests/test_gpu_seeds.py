@@ -172,3 +172,28 @@ def test_bench_size_sampled(bsw, ctx, oracle_lib):
     got = run_device(bsw, ctx, w, with_rev=True)
     idx = np.sort(np.random.default_rng(17).choice(len(w["seeds"]), 3000, replace=False))
     assert_same(got[idx], reference(w, seeds=w["seeds"][idx]), "sample")
+
+
+def test_seed_tuner_keeps_results_and_caches_its_own_entry(bsw, oracle_lib, tmp_path):
+    import json
+    import torch
+    w = synth.seed_workload(4000, seed=18)
+    want = reference(w)
+    dev = bsw.seeds_to_device(w["reads"], w["read_off"], w["ref"], w["seeds"],
+                              with_ref_rev=True)
+    out = torch.zeros(len(w["seeds"]) * 32, dtype=torch.uint8, device="cuda")
+    cache = str(tmp_path / "tune.json")
+    with bsw.Context(tune_cache=cache) as c:
+        ms, shape = c.tune_seeds(dev, w["scoring"], out, reps=1)
+        assert ms > 0 and shape["side_streams"] in (1, 2, 4)
+        assert_same(out.cpu().numpy().view(bsw.SEED_RESULT_DTYPE), want, "tuner call")
+        pairs_shape = c.tune_info()
+    entries = json.load(open(cache))
+    (key, val), = entries.items()
+    assert key.endswith(":seeds") and val["nside"] == shape["side_streams"]
+    # a new context takes it for seed calls only
+    with bsw.Context(tune_cache=cache) as c2:
+        out.zero_()
+        c2.extend_seeds_device(dev, w["scoring"], out)
+        assert_same(out.cpu().numpy().view(bsw.SEED_RESULT_DTYPE), want, "cached shape")
+        assert c2.tune_info() == pairs_shape
