@@ -203,9 +203,10 @@ def main():
                          "hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single "
-              "MI355X and has no multi-GPU path (pairs are independent; see "
-              "DESIGN.md for how batches would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single "
+              "MI355X and has no multi-GPU path (pairs are independent, so a "
+              "batch would shard into equal-work ranges, one per GPU, with no "
+              "collective).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
