@@ -183,6 +183,29 @@ def seed_driver(bsw, synth, torch, np, tune_cache, steps, warmup, tune=True):
     return leg, sw
 
 
+def seed_cpu_baseline(np, sw, seconds):
+    """The reference seed driver on the host cores, on a random sample of the
+    seeds sized for about `seconds` of work."""
+    from oracle import seeds as oseeds
+    threads = min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(0)
+    ns = len(sw["seeds"])
+
+    def run(m):
+        idx = np.sort(rng.choice(ns, size=m, replace=False))
+        t = time.perf_counter()
+        oseeds.extend_seeds(sw["reads"], sw["read_off"], sw["ref"], sw["seeds"][idx],
+                            sw["scoring"], n_threads=threads)
+        return time.perf_counter() - t
+
+    m0 = min(ns, 20000)
+    rate = m0 / run(m0)
+    m = int(min(ns, max(m0, rate * seconds)))
+    dt = run(m)
+    return {"value": round(m / dt, 1), "unit": "seeds/s", "cores": threads, "kind": "oracle",
+            "sample": f"{m} random seeds of the {ns}, {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +217,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-seeds", action="store_true",
                     help="skip the read-level seed driver leg")
+    ap.add_argument("--seeds-only", action="store_true",
+                    help="run only the seed driver leg and print it as the JSON line "
+                         "(for profiling it alone)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shapes (skip the autotuner)")
@@ -221,6 +247,15 @@ def main():
         torch.cuda.synchronize()
         del x, y
     workers = min(16, os.cpu_count() or 1)
+    if args.seeds_only:
+        import tempfile
+        tc = os.path.join(tempfile.mkdtemp(prefix="bsw_tune_"), "tune.json")
+        leg, sw = seed_driver(bsw, synth, torch, np, tc, args.steps, args.warmup,
+                              tune=not args.no_tune)
+        if not args.no_cpu:
+            leg["cpu_baseline"] = seed_cpu_baseline(np, sw, args.cpu_seconds)
+        print(json.dumps(leg), flush=True)
+        return
     t0 = time.time()
     batch = synth.batched_mix(n=args.pairs, workers=workers)
     n = len(batch["h0"])
@@ -341,17 +376,7 @@ def main():
                          f"{int(sd['cells'].sum())} cells, {dt:.1f} s"}
         log(f"cpu: {cpu}")
         if seeds_leg is not None:
-            from oracle import seeds as oseeds
-            ns = len(sw["seeds"])
-            m = min(ns, 40000)
-            idx = np.sort(rng.choice(ns, size=m, replace=False))
-            t = time.perf_counter()
-            oseeds.extend_seeds(sw["reads"], sw["read_off"], sw["ref"], sw["seeds"][idx],
-                                sw["scoring"], n_threads=threads)
-            dt = time.perf_counter() - t
-            seeds_leg["cpu_baseline"] = {
-                "value": round(m / dt, 1), "unit": "seeds/s", "cores": threads,
-                "kind": "oracle", "sample": f"{m} random seeds of the {ns}, {dt:.1f} s"}
+            seeds_leg["cpu_baseline"] = seed_cpu_baseline(np, sw, args.cpu_seconds)
             log(f"cpu seeds: {seeds_leg['cpu_baseline']}")
 
     res = {
