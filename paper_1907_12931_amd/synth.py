@@ -418,6 +418,134 @@ def seed_workload(n_reads=2000, seed=5, read_len=151, ref_len=1 << 20, min_seed=
             "seeds": np.concatenate(seeds), "scoring": BWA_DEFAULT}
 
 
+# ---------------------------------------------------------------------------
+# Suffix-array lookup inputs: a reference with repeat families, the text the
+# mapper indexes (the reference and its reverse complement), its suffix
+# array, and SA intervals of seed-length patterns.
+
+SA_INTERVAL = np.dtype([("k", "<u8"), ("s", "<u8")])  # rows [k, k + s) of the SA
+_KEY_BASES = 21  # bases per 64-bit sort key (3 bits each, 0 = end of text)
+
+
+def _prefix_keys(t, n):
+    """Key of every suffix i of t (codes 0..3) and of the empty suffix n:
+    its first 21 bases as 3-bit codes 1..4, 0 past the end."""
+    pad = np.concatenate([t.astype(np.uint64) + 1, np.zeros(_KEY_BASES, np.uint64)])
+    key = np.zeros(n + 1, dtype=np.uint64)
+    for d in range(_KEY_BASES):
+        key = (key << np.uint64(3)) | pad[d:d + n + 1]
+    return key
+
+
+def suffix_array(t):
+    """Suffix array of t followed by the end marker (smaller than every
+    base): n + 1 int64 entries, S[0] = n.  Prefix doubling with group
+    refinement: suffixes are sorted by their first 21 bases, then every
+    group of still-equal suffixes is split by the rank of the suffix h bases
+    further on, h doubling each round, until every group is a singleton."""
+    t = np.asarray(t, dtype=np.uint8)
+    n = len(t)
+    key = _prefix_keys(t, n)
+    order = np.argsort(key)
+    sk = key[order]
+    del key
+    new = np.ones(n + 1, dtype=bool)
+    new[1:] = sk[1:] != sk[:-1]
+    del sk
+    head = np.maximum.accumulate(np.where(new, np.arange(n + 1), 0))
+    rank = np.empty(n + 1, dtype=np.int64)
+    rank[order] = head
+    h = _KEY_BASES
+    while True:
+        starts = np.nonzero(new)[0]
+        size = np.diff(np.append(starts, n + 1))
+        todo = np.repeat(size, size) > 1
+        if not todo.any():
+            break
+        pos = np.nonzero(todo)[0]
+        idx, g = order[pos], head[pos]
+        sec = np.where(idx + h <= n, rank[np.minimum(idx + h, n)], -1)
+        o = np.lexsort((sec, g))
+        idx, g, sec = idx[o], g[o], sec[o]
+        order[pos] = idx
+        nh = np.ones(len(idx), dtype=bool)
+        nh[1:] = (g[1:] != g[:-1]) | (sec[1:] != sec[:-1])
+        hh = np.maximum.accumulate(np.where(nh, pos, 0))
+        head[pos] = hh
+        rank[idx] = hh
+        new[pos] = nh
+        h *= 2
+    return order.astype(np.int64)
+
+
+def revcomp(t):
+    t = np.asarray(t, dtype=np.uint8)
+    return (3 - t[::-1]).astype(np.uint8)
+
+
+def repeat_reference(n, seed, repeat_frac=0.12, copies=(2, 300), length=(100, 400),
+                     divergence=(0.0, 0.05)):
+    """Uniform random ACGT of length n with repeat families written over
+    about repeat_frac of it: each family a random consensus of length U[length]
+    copied log-U[copies] times, each copy with its own substitution rate
+    U[divergence], at random places."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ref = _random_bases(rng, n)
+    covered = 0
+    while covered < repeat_frac * n:
+        L = int(rng.integers(length[0], length[1] + 1))
+        c = int(np.exp(rng.uniform(np.log(copies[0]), np.log(copies[1]))))
+        cons = _random_bases(rng, L)
+        for _ in range(c):
+            p = int(rng.integers(0, n - L))
+            cp = cons.copy()
+            sub = rng.random(L) < rng.uniform(*divergence)
+            cp[sub] = (cp[sub] + rng.integers(1, 4, size=int(sub.sum()), dtype=np.uint8)) % 4
+            ref[p:p + L] = cp
+        covered += L * c
+    return ref
+
+
+def sa_intervals(text, sa, n_iv, seed, lengths=(19, 21)):
+    """SA intervals of n_iv patterns: text[p, p + L) for p uniform over the
+    forward half of the text (the reference) and L uniform in lengths, so
+    each interval holds every occurrence of the pattern on either strand."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = len(text)
+    allkey = _prefix_keys(np.asarray(text, dtype=np.uint8), n)
+    skey = allkey[sa]
+    half = n // 2
+    L = rng.integers(lengths[0], lengths[1] + 1, size=n_iv)
+    p = rng.integers(0, half - lengths[1], size=n_iv)
+    iv = np.zeros(n_iv, dtype=SA_INTERVAL)
+    pkey = allkey[p]
+    del allkey
+    for l in range(lengths[0], lengths[1] + 1):
+        m = L == l
+        sh = np.uint64(3 * (_KEY_BASES - l))
+        tk = skey >> sh
+        lo = np.searchsorted(tk, pkey[m] >> sh, side="left")
+        hi = np.searchsorted(tk, pkey[m] >> sh, side="right")
+        iv["k"][m] = lo
+        iv["s"][m] = hi - lo
+    return iv, p, L
+
+
+def sa_workload(ref_len=1 << 14, n_iv=2000, seed=6, **kw):
+    """Reference with repeats (seed), the indexed text ref + revcomp(ref),
+    its suffix array and n_iv SA intervals (seed + 1)."""
+    ref = repeat_reference(ref_len, seed, **kw)
+    text = np.concatenate([ref, revcomp(ref)])
+    sa = suffix_array(text)
+    iv, p, L = sa_intervals(text, sa, n_iv, seed + 1)
+    return {"ref": ref, "text": text, "sa": sa, "iv": iv, "pattern_pos": p, "pattern_len": L}
+
+
+# the lookup's benchmark workload: a 32 Mbase reference (64 Mbase indexed
+# text, a 512 MB suffix array) and 4 M intervals
+SA_BENCH = dict(ref_len=1 << 25, n_iv=4_000_000, seed=6)
+
+
 # the read-level driver's benchmark workload: 500,000 reads of 151 bases
 # drawn from a 64 Mbase reference (about 1.3 M seeds)
 SEED_BENCH = dict(n_reads=500_000, seed=5, ref_len=1 << 26)
