@@ -40,14 +40,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_from_profile(kernel, cells):
+def traffic_from_profile(kernel, work, profile="bsw"):
     """HBM bytes per launch of a kernel from the committed counter profile
     (FETCH_SIZE + WRITE_SIZE, calibrated on a plain streaming kernel), if
     the profile was taken on the current kernel source and the same work
-    (its cells per launch); else None."""
+    per launch (cells for the extension kernels, algorithmic bytes for the
+    suffix-array lookup); else None."""
     import hashlib
     import re
-    src = os.path.join(ROOT, "paper_1907_12931_amd", "csrc", "bsw_kernels.hip")
+    src_name, work_field = {"bsw": ("bsw_kernels.hip", "cells_per_launch"),
+                            "sal": ("bsw_sal_kernels.hip", "alg_bytes_per_launch")}[profile]
+    src = os.path.join(ROOT, "paper_1907_12931_amd", "csrc", src_name)
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     prof_dir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(prof_dir):
@@ -58,7 +61,7 @@ def traffic_from_profile(kernel, cells):
         text = open(os.path.join(prof_dir, name)).read()
         fields = dict(re.findall(r"^- (\w+): `([^`]*)`", text, flags=re.M))
         if (fields.get("kernel") == kernel and fields.get("source_sha256") == digest
-                and fields.get("cells_per_launch") == str(cells)
+                and fields.get(work_field) == str(work)
                 and "traffic_bytes_per_launch" in fields):
             return int(fields["traffic_bytes_per_launch"])
     return None
@@ -206,6 +209,77 @@ def seed_cpu_baseline(np, sw, seconds):
             "sample": f"{m} random seeds of the {ns}, {dt:.1f} s"}
 
 
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def sa_lookup(bsw, synth, torch, np, steps, warmup):
+    """Suffix-array lookup (Eq. 1) of the benchmark intervals against the
+    resident suffix array of the benchmark text."""
+    t0 = time.time()
+    w = synth.sa_workload(**synth.SA_BENCH)
+    n = len(w["iv"])
+    total = int(w["iv"]["s"].astype(np.int64).sum())
+    log(f"built a {len(w['sa'])}-entry suffix array and {n} intervals in "
+        f"{time.time() - t0:.1f}s")
+    sa = torch.from_numpy(w["sa"]).cuda()
+    iv = torch.from_numpy(np.ascontiguousarray(w["iv"]).view(np.uint8)).cuda()
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    pos = torch.empty(total, dtype=torch.int64, device="cuda")
+    ctx = bsw.Context()
+    for _ in range(max(1, warmup)):
+        assert ctx.sa_lookup_device(sa, iv, off, pos) == total
+    torch.cuda.synchronize()
+    tms = []
+    t = time.perf_counter()
+    for _ in range(steps):
+        ctx.sa_lookup_device(sa, iv, off, pos)
+        tms.append(ctx.last_timing())
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / steps
+    ctx.close()
+    tm = np.mean(np.asarray(tms), axis=0)
+    # the gather's algorithmic bytes: per coordinate an 8-byte entry of S
+    # read and an 8-byte coordinate written; per interval its 8-byte start
+    # and 8-byte offset read and the offset written back
+    alg = 16 * total + 24 * n
+    gbs = alg / (tm[2] / 1e3) / 1e9
+    kernel = "bsw::k_sal_gather"
+    leg = {"value": round(total / wall, 1), "unit": "SA coordinates/s",
+           "ms_per_step": round(wall * 1e3, 3), "device_ms": round(float(tm[0]), 3),
+           "check_scan_ms": round(float(tm[1]), 3), "gather_ms": round(float(tm[2]), 3),
+           "intervals": n, "coordinates": total, "sa_entries": len(w["sa"]),
+           "workload": f"suffix array of a {len(w['text'])}-base text (a "
+                       f"{len(w['ref'])}-base reference with repeat families, 12% of it, "
+                       "2-300 copies at 0-5% divergence, and its reverse complement); "
+                       f"{n} intervals of 19-21-base patterns drawn from the reference",
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": traffic_from_profile(kernel, alg, profile="sal"),
+                        "kernel": kernel, "alg_bytes_per_launch": alg}}
+    return leg, w
+
+
+def sal_cpu_baseline(np, w, seconds):
+    """The reference lookup on the host, on a random sample of intervals
+    sized for about `seconds` of work."""
+    from oracle import sal
+    rng = np.random.default_rng(0)
+    n = len(w["iv"])
+
+    def run(m):
+        idx = np.sort(rng.choice(n, size=m, replace=False))
+        t = time.perf_counter()
+        _, out = sal.lookup(w["sa"], w["iv"][idx])
+        return len(out), time.perf_counter() - t
+
+    c0, dt0 = run(min(n, 20000))
+    m = int(min(n, max(20000, 20000 / dt0 * seconds)))
+    c, dt = run(m)
+    return {"value": round(c / dt, 1), "unit": "SA coordinates/s", "cores": 1,
+            "kind": "oracle", "sample": f"{m} random intervals of the {n}, {c} "
+                                        f"coordinates, {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +291,10 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-seeds", action="store_true",
                     help="skip the read-level seed driver leg")
+    ap.add_argument("--no-sal", action="store_true",
+                    help="skip the suffix-array lookup leg")
+    ap.add_argument("--sal-only", action="store_true",
+                    help="run only the suffix-array lookup leg and print it as the JSON line")
     ap.add_argument("--seeds-only", action="store_true",
                     help="run only the seed driver leg and print it as the JSON line "
                          "(for profiling it alone)")
@@ -247,6 +325,12 @@ def main():
         torch.cuda.synchronize()
         del x, y
     workers = min(16, os.cpu_count() or 1)
+    if args.sal_only:
+        leg, w = sa_lookup(bsw, synth, torch, np, args.steps, args.warmup)
+        if not args.no_cpu:
+            leg["cpu_baseline"] = sal_cpu_baseline(np, w, args.cpu_seconds)
+        print(json.dumps(leg), flush=True)
+        return
     if args.seeds_only:
         import tempfile
         tc = os.path.join(tempfile.mkdtemp(prefix="bsw_tune_"), "tune.json")
@@ -327,6 +411,11 @@ def main():
                    for r in (0.5, 0.8)}
         log(f"serving: {serving}")
 
+    sal_leg = sal_w = None
+    if not args.no_sal:
+        sal_leg, sal_w = sa_lookup(bsw, synth, torch, np, args.steps, args.warmup)
+        log(f"sa lookup: {sal_leg}")
+
     seeds_leg = None
     if not args.no_seeds:
         seeds_leg, sw = seed_driver(bsw, synth, torch, np, tune_cache, args.steps,
@@ -378,6 +467,9 @@ def main():
         if seeds_leg is not None:
             seeds_leg["cpu_baseline"] = seed_cpu_baseline(np, sw, args.cpu_seconds)
             log(f"cpu seeds: {seeds_leg['cpu_baseline']}")
+        if sal_leg is not None:
+            sal_leg["cpu_baseline"] = sal_cpu_baseline(np, sal_w, args.cpu_seconds)
+            log(f"cpu sa lookup: {sal_leg['cpu_baseline']}")
 
     res = {
         "metric": "GCUPS (bit-exact vs oracle) batched vs plain; p50/p99 latency under serving",
@@ -391,7 +483,8 @@ def main():
                    "pairs": n, "cells": cells, "path": "batched",
                    "dp_launches": b["dp_launches"], "graph": True, "tuned": tuned,
                    "prep_bin_ms": round(p["prep_ms"], 3)},
-        "plain": plain, "serving": serving, "seed_driver": seeds_leg, "roofline": roofline,
+        "plain": plain, "serving": serving, "seed_driver": seeds_leg, "sa_lookup": sal_leg,
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

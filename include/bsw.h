@@ -370,6 +370,42 @@ int bsw_ctx_tune_seeds(bsw_ctx* ctx, const uint8_t* reads, uint64_t reads_len,
                        bsw_seed_result* out, int32_t reps, double* best_ms,
                        int32_t out3[3]);
 
+/* ------------------------------------------------------------------------
+ * Suffix-array lookup (SAL, Sec. 4.5, Eq. (1)).  The seeding step finds,
+ * for each seed, its SA interval: the rows of the index's sorted-suffix
+ * order (Sec. 2.2) whose suffixes start with the seed.  SAL turns every row
+ * i of an interval into the seed's coordinate in the indexed text,
+ * j = S[i], read from the uncompressed suffix array kept in device memory
+ * (8 bytes per text position: a human reference and its reverse complement,
+ * 6.2 G positions, take about 50 GB, which one MI355X holds).
+ * ---------------------------------------------------------------------- */
+
+/* Rows [k, k + s) of the suffix array (16 bytes). */
+typedef struct bsw_sa_interval {
+  uint64_t k;
+  uint64_t s;
+} bsw_sa_interval;
+
+/* Device form only (the suffix array stays resident): sa (sa_len entries),
+ * iv (n intervals), out_off (n + 1 entries) and out_pos (out_cap entries)
+ * are device pointers.  Interval m's coordinates S[k], ..., S[k + s - 1]
+ * are written to out_pos[out_off[m] .. out_off[m + 1]), out_off[0] = 0, in
+ * interval order.  Checks on the device: every interval lies inside the
+ * suffix array (k + s <= sa_len) and holds at most 2^32 rows, and the total
+ * fits out_cap (at most 2^40); a failed check
+ * writes nothing and returns BSW_EINVAL naming the first bad interval, or
+ * BSW_ETOOBIG with the total needed.  *total (host, nullable) receives the
+ * number of coordinates (blocking calls; after an asynchronous call it is
+ * out_off[n]).  stream and async as for bsw_extend_batch_device.
+ * bsw_ctx_last_timing then gives [0] = the whole call, [1] = checks and the
+ * offset scan, [2] = the gather, [3] = 0.  Arena use: 8 (n + 1) bytes, 8
+ * bytes per 2,048 intervals and 8 bytes per 256 entries of out_cap.  n = 0
+ * is a no-op (*total = 0). */
+int bsw_sa_lookup_device(bsw_ctx* ctx, const int64_t* sa, uint64_t sa_len,
+                         const bsw_sa_interval* iv, int64_t n, uint64_t* out_off,
+                         int64_t* out_pos, uint64_t out_cap, uint64_t* total,
+                         void* stream, int32_t async);
+
 /* Text of the calling thread's most recent error ("" if none). */
 const char* bsw_last_error(void);
 

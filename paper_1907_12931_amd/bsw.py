@@ -68,6 +68,8 @@ SEED_DTYPE = np.dtype([("read", "<i4"), ("qb", "<i4"), ("qe", "<i4"), ("h0", "<i
 SEED_RESULT_DTYPE = np.dtype([("score", "<i4"), ("qbeg", "<i4"), ("qend", "<i4"),
                               ("how", "<i4"), ("rbeg", "<i8"), ("rend", "<i8")])
 END_LOCAL, END_READ, END_NONE = 0, 1, 2
+# suffix-array lookup (bsw_sa_interval): rows [k, k + s)
+SA_INTERVAL_DTYPE = np.dtype([("k", "<u8"), ("s", "<u8")])
 
 _lib = None
 _VP = ctypes.c_void_p
@@ -131,6 +133,10 @@ def lib():
             _VP, _VP, ctypes.c_uint64, _VP, ctypes.c_int64, _VP, _VP, ctypes.c_uint64,
             _VP, ctypes.c_int64, ctypes.POINTER(Params), _VP, ctypes.c_int32,
             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+        L.bsw_sa_lookup_device.restype = ctypes.c_int
+        L.bsw_sa_lookup_device.argtypes = [
+            _VP, _VP, ctypes.c_uint64, _VP, ctypes.c_int64, _VP, _VP, ctypes.c_uint64,
+            ctypes.POINTER(ctypes.c_uint64), _VP, ctypes.c_int32]
         L.bsw_ctx_tune_info.restype = ctypes.c_int
         L.bsw_ctx_tune_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
         L.bsw_server_create.restype = ctypes.c_int
@@ -284,6 +290,21 @@ class Context:
             dev["ref"].numel(), dev["seeds"].data_ptr(), n, params, out.data_ptr(), reps,
             ctypes.byref(ms), v))
         return ms.value, {"side_streams": v[0], "occ8_pct": v[1], "spec16": v[2]}
+
+    def sa_lookup_device(self, sa, iv, out_off, out_pos, stream=None, async_=False):
+        """Suffix-array lookup (``bsw_sa_lookup_device``): sa an int64 tensor,
+        iv a tensor of n*16 bytes (SA_INTERVAL_DTYPE records), out_off an
+        int64 tensor of n + 1 entries, out_pos an int64 tensor (its length is
+        the capacity).  Returns the number of coordinates (None if async)."""
+        n = iv.numel() * iv.element_size() // SA_INTERVAL_DTYPE.itemsize
+        tot = ctypes.c_uint64(0)
+        s = stream.cuda_stream if stream is not None else None
+        _check(lib().bsw_sa_lookup_device(
+            self._h, sa.data_ptr(), sa.numel(), iv.data_ptr(), n, out_off.data_ptr(),
+            out_pos.data_ptr() if out_pos is not None and out_pos.numel() else None,
+            out_pos.numel() if out_pos is not None else 0, ctypes.byref(tot), s,
+            1 if async_ else 0))
+        return None if async_ else tot.value
 
     def last_cells(self):
         """Band cells settled by the last completed call (all its passes)."""

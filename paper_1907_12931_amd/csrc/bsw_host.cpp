@@ -222,6 +222,7 @@ struct bsw_ctx {
   hipStream_t pending_stream = nullptr;
   int (*pending_done)(bsw_ctx*) = nullptr;  // completion check of that call
   SeedState* seed = nullptr;                // read-level seed driver
+  SalState* sal = nullptr;                  // suffix-array lookup
   bool graph_call = false;  // the last call ran as a graph replay
   Status* last_st = nullptr;  // device status block of the last call
   double timing[4] = {0, 0, 0, 0};
@@ -796,6 +797,8 @@ double* ctx_timing(bsw_ctx* c) { return c->timing; }
 
 void ctx_add_cells(bsw_ctx* c, unsigned long long cells) { c->last_cells += cells; }
 
+void ctx_set_cells(bsw_ctx* c, unsigned long long cells) { c->last_cells = cells; }
+
 int ctx_set_device(bsw_ctx* c) { return set_device(c); }
 
 void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*)) {
@@ -805,6 +808,8 @@ void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*)) {
 }
 
 SeedState*& ctx_seed_state(bsw_ctx* c) { return c->seed; }
+
+SalState*& ctx_sal_state(bsw_ctx* c) { return c->sal; }
 
 void ctx_set_kind(bsw_ctx* c, int kind) { c->kind = kind; }
 
@@ -914,6 +919,7 @@ void bsw_ctx_destroy(bsw_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->pending) (void)hipStreamSynchronize(c->pending_stream);
   seed_state_free(c->seed);
+  sal_state_free(c->sal);
   c->ws.release();
   c->in.release();
   c->res.release();

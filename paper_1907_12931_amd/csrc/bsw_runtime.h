@@ -109,6 +109,7 @@ int ctx_launches(const bsw_ctx* c);
 // ctx_finish).
 double* ctx_timing(bsw_ctx* c);
 void ctx_add_cells(bsw_ctx* c, unsigned long long cells);
+void ctx_set_cells(bsw_ctx* c, unsigned long long cells);
 int ctx_set_device(bsw_ctx* c);
 // Mark the context as having an asynchronous call in flight on s whose
 // completion is checked by done (bsw_ctx_wait calls it).
@@ -132,6 +133,10 @@ Tune ctx_shape(const bsw_ctx* c, int kind);
 struct SeedState;
 SeedState*& ctx_seed_state(bsw_ctx* c);
 void seed_state_free(SeedState* s);
+// State of the suffix-array lookup, likewise.
+struct SalState;
+SalState*& ctx_sal_state(bsw_ctx* c);
+void sal_state_free(SalState* s);
 
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
