@@ -49,7 +49,8 @@ def traffic_from_profile(kernel, work, profile="bsw"):
     import hashlib
     import re
     src_name, work_field = {"bsw": ("bsw_kernels.hip", "cells_per_launch"),
-                            "sal": ("bsw_sal_kernels.hip", "alg_bytes_per_launch")}[profile]
+                            "sal": ("bsw_sal_kernels.hip", "alg_bytes_per_launch"),
+                            "fm": ("bsw_fm_kernels.hip", "alg_bytes_per_launch")}[profile]
     src = os.path.join(ROOT, "paper_1907_12931_amd", "csrc", src_name)
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     prof_dir = os.path.join(ROOT, "profiles")
@@ -259,6 +260,80 @@ def sa_lookup(bsw, synth, torch, np, steps, warmup):
     return leg, w
 
 
+def fm_search(bsw, synth, torch, np, w, steps, warmup):
+    """Bi-interval backward search of the benchmark patterns over the FM
+    index of the lookup's two-strand text."""
+    t0 = time.time()
+    entries, meta = bsw.fm_build(w["text"], w["sa"])
+    pat, off = synth.fm_patterns(w["text"], synth.FM_BENCH_PATTERNS, seed=44)
+    n = len(off) - 1
+    log(f"built the FM index ({len(entries)} entries) and {n} patterns in "
+        f"{time.time() - t0:.1f}s")
+    E = torch.from_numpy(entries.view(np.uint8)).cuda()
+    pd = torch.from_numpy(pat).cuda()
+    od = torch.from_numpy(off.astype(np.uint64).view(np.int64)).cuda()
+    out = torch.empty(n * bsw.BI_INTERVAL_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    ctx = bsw.Context()
+    for _ in range(max(1, warmup)):
+        ctx.fm_backward_search_device(E, meta, pd, od, out)
+    torch.cuda.synchronize()
+    ms = []
+    t = time.perf_counter()
+    for _ in range(steps):
+        ctx.fm_backward_search_device(E, meta, pd, od, out)
+        ms.append(ctx.last_timing()[0])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / steps
+    ctx.close()
+    res = out.cpu().numpy().view(bsw.BI_INTERVAL_DTYPE)
+    L = np.diff(off.astype(np.int64))
+    m = res["matched"].astype(np.int64)
+    # extension steps run: every matched base, plus the step whose interval
+    # came out empty (a pattern stopped by an N takes no step for it)
+    stop = m < L
+    nxt = np.where(stop, pat[np.minimum(off[1:].astype(np.int64) - m - 1, len(pat) - 1)], 4)
+    steps_run = int(m.sum() + np.count_nonzero(stop & (nxt < 4)))
+    kms = float(np.mean(ms))
+    alg = 2 * 64 * steps_run  # two 64-byte entries read per step
+    gbs = alg / (kms / 1e3) / 1e9
+    return {"value": round(n / wall, 1), "unit": "patterns/s",
+            "extensions_per_s": round(steps_run / wall, 1), "ms_per_step": round(wall * 1e3, 3),
+            "kernel_ms": round(kms, 3), "patterns": n, "extension_steps": steps_run,
+            "fully_matched": int(np.count_nonzero(~stop)),
+            "index_bytes": int(entries.nbytes),
+            "workload": f"{n} patterns of 32 bases from the {len(w['ref'])}-base reference "
+                        "(2% substitutions, 0.5% N) against the FM index of it and its "
+                        f"reverse complement ({len(w['sa'])} rows, 64-byte entries of 32 rows)",
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": traffic_from_profile("bsw::k_fm_search", alg, profile="fm"),
+                         "kernel": "bsw::k_fm_search",
+                         "alg_bytes_per_launch": alg}}
+
+
+def fm_cpu_baseline(np, synth, w, seconds):
+    """The reference backward search on the host, on a random sample of the
+    benchmark patterns sized for about `seconds` of work."""
+    from oracle import fm, sal
+    pat, off = synth.fm_patterns(w["text"], synth.FM_BENCH_PATTERNS, seed=44)
+    txt = sal.to_text(w["text"]) + "$"
+    rng = np.random.default_rng(0)
+    n = len(off) - 1
+
+    def run(m):
+        idx = rng.choice(n, size=m, replace=False)
+        t = time.perf_counter()
+        for j in idx:
+            fm.backward_search(w["text"], w["sa"], pat[off[j]:off[j + 1]], txt)
+        return time.perf_counter() - t
+
+    dt0 = run(200)
+    m = int(min(n, max(200, 200 / dt0 * seconds)))
+    dt = run(m)
+    return {"value": round(m / dt, 1), "unit": "patterns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{m} random patterns of the {n}, {dt:.1f} s"}
+
+
 def sal_cpu_baseline(np, w, seconds):
     """The reference lookup on the host, on a random sample of intervals
     sized for about `seconds` of work."""
@@ -295,6 +370,9 @@ def main():
                     help="skip the suffix-array lookup leg")
     ap.add_argument("--sal-only", action="store_true",
                     help="run only the suffix-array lookup leg and print it as the JSON line")
+    ap.add_argument("--fm-only", action="store_true",
+                    help="run only the FM-index backward search leg and print it as the "
+                         "JSON line")
     ap.add_argument("--seeds-only", action="store_true",
                     help="run only the seed driver leg and print it as the JSON line "
                          "(for profiling it alone)")
@@ -325,6 +403,13 @@ def main():
         torch.cuda.synchronize()
         del x, y
     workers = min(16, os.cpu_count() or 1)
+    if args.fm_only:
+        w = synth.sa_workload(**synth.SA_BENCH)
+        leg = fm_search(bsw, synth, torch, np, w, args.steps, args.warmup)
+        if not args.no_cpu:
+            leg["cpu_baseline"] = fm_cpu_baseline(np, synth, w, args.cpu_seconds)
+        print(json.dumps(leg), flush=True)
+        return
     if args.sal_only:
         leg, w = sa_lookup(bsw, synth, torch, np, args.steps, args.warmup)
         if not args.no_cpu:
@@ -415,6 +500,10 @@ def main():
     if not args.no_sal:
         sal_leg, sal_w = sa_lookup(bsw, synth, torch, np, args.steps, args.warmup)
         log(f"sa lookup: {sal_leg}")
+        fm_leg = fm_search(bsw, synth, torch, np, sal_w, args.steps, args.warmup)
+        log(f"fm search: {fm_leg}")
+    else:
+        fm_leg = None
 
     seeds_leg = None
     if not args.no_seeds:
@@ -470,6 +559,8 @@ def main():
         if sal_leg is not None:
             sal_leg["cpu_baseline"] = sal_cpu_baseline(np, sal_w, args.cpu_seconds)
             log(f"cpu sa lookup: {sal_leg['cpu_baseline']}")
+            fm_leg["cpu_baseline"] = fm_cpu_baseline(np, synth, sal_w, args.cpu_seconds)
+            log(f"cpu fm search: {fm_leg['cpu_baseline']}")
 
     res = {
         "metric": "GCUPS (bit-exact vs oracle) batched vs plain; p50/p99 latency under serving",
@@ -484,6 +575,7 @@ def main():
                    "dp_launches": b["dp_launches"], "graph": True, "tuned": tuned,
                    "prep_bin_ms": round(p["prep_ms"], 3)},
         "plain": plain, "serving": serving, "seed_driver": seeds_leg, "sa_lookup": sal_leg,
+        "fm_search": fm_leg,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

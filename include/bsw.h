@@ -406,6 +406,60 @@ int bsw_sa_lookup_device(bsw_ctx* ctx, const int64_t* sa, uint64_t sa_len,
                          int64_t* out_pos, uint64_t out_cap, uint64_t* total,
                          void* stream, int32_t async);
 
+/* ------------------------------------------------------------------------
+ * FM-index backward search (Sec. 4.1, Algorithms 1 and 2; the index layout
+ * of Sec. 4.4).  The index covers a text T holding both strands (a
+ * reference followed by its reverse complement), with the end marker $
+ * after it.  Its occurrence table is cut into buckets of BSW_FM_ETA = 32
+ * rows; each bucket is one 64-byte entry: the counts of A, C, G, T in the
+ * BWT before the bucket, the bucket's 32 BWT symbols as bytes (0..3, 4 for
+ * $, 5 past the last row) and 16 bytes of padding, so one entry is one
+ * cache line.  O(c, t) = count[c] of entry t / 32 plus the occurrences of c
+ * among the first t % 32 + 1 symbols of that entry (Algorithm 1).
+ * ---------------------------------------------------------------------- */
+#define BSW_FM_ETA 32
+
+typedef struct bsw_fm_entry {
+  uint32_t count[4];  /* occurrences of A, C, G, T in BWT rows before the bucket */
+  uint8_t  bwt[32];   /* the bucket's BWT symbols                               */
+  uint8_t  pad_[16];
+} bsw_fm_entry;
+
+typedef struct bsw_fm_meta {
+  uint64_t rows;     /* |T| + 1 (rows of the BW matrix)                      */
+  uint64_t C[4];     /* first row of the suffixes that start with A, C, G, T */
+  uint64_t primary;  /* row whose suffix is all of T (its BWT symbol is $)   */
+  uint64_t entries;  /* ceil(rows / 32)                                      */
+} bsw_fm_meta;
+
+/* Bi-interval of a pattern X (32 bytes): X occupies rows [k, k + s), its
+ * reverse complement rows [l, l + s); matched = length of the longest
+ * suffix of X that occurs in T.  k = l = s = 0 unless all of X occurs. */
+typedef struct bsw_bi_interval {
+  uint64_t k, l, s;
+  int32_t matched;
+  int32_t pad_;
+} bsw_bi_interval;
+
+/* Build the index on the host from T (n codes 0..3) and the suffix array of
+ * T$ (n + 1 entries, a permutation of 0..n with sa[0] = n).  entries has
+ * room for ceil((n + 1) / 32) entries; meta receives the rest.  Returns
+ * BSW_EINVAL for a code > 3 or an entry of sa outside 0..n. */
+int bsw_fm_build(const uint8_t* text, uint64_t n, const int64_t* sa, bsw_fm_entry* entries,
+                 bsw_fm_meta* meta);
+
+/* Backward search of n patterns (device memory): pattern m is
+ * pat[pat_off[m] .. pat_off[m + 1]), codes 0..4 (an N ends the search);
+ * entries is the index in device memory (meta->entries entries), meta host
+ * memory.  Every pattern is extended from its last base to its first by the
+ * bi-interval update of Algorithm 2, stopping when the interval empties;
+ * out[m] receives its bi-interval.  stream and async as for
+ * bsw_extend_batch_device.  bsw_ctx_last_timing [0] = the search kernel. */
+int bsw_fm_backward_search_device(bsw_ctx* ctx, const bsw_fm_entry* entries,
+                                  const bsw_fm_meta* meta, const uint8_t* pat,
+                                  const uint64_t* pat_off, int64_t n, bsw_bi_interval* out,
+                                  void* stream, int32_t async);
+
 /* Text of the calling thread's most recent error ("" if none). */
 const char* bsw_last_error(void);
 

@@ -54,16 +54,25 @@ def bi_interval(text, sa, x):
     return k, l, s
 
 
-def backward_search(text, sa, pattern):
+def backward_search(text, sa, pattern, txt=None):
     """(k, l, s, matched): the bi-interval of the pattern (zeros unless all
-    of it occurs) and the length of its longest occurring suffix."""
+    of it occurs) and the length of its longest occurring suffix.  The
+    intervals are found by bisection over the sorted rows (txt: the text as
+    a string followed by '$', made here when not given)."""
     p = np.asarray(pattern, dtype=np.uint8)
+    if txt is None:
+        txt = sal.to_text(text) + "$"
     matched = 0
     for m in range(1, len(p) + 1):
-        if (p[len(p) - m:] > 3).any() or sal.sa_interval(sa, text, p[len(p) - m:])[1] == 0:
+        suf = p[len(p) - m:]
+        if suf[0] > 3 or sal.sa_interval_sorted(sa, txt, sal.to_text(suf))[1] == 0:
             break
         matched = m
     if matched < len(p):
         return 0, 0, 0, matched
-    k, l, s = bi_interval(text, sa, p)
+    if len(p) == 0:
+        return 0, 0, len(sa), 0
+    k, s = sal.sa_interval_sorted(sa, txt, sal.to_text(p))
+    l, s2 = sal.sa_interval_sorted(sa, txt, sal.to_text(revcomp(p)))
+    assert s2 == s
     return k, l, s, matched

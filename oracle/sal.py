@@ -20,14 +20,17 @@ one in the tests.
 """
 from __future__ import annotations
 
+import bisect
+
 import numpy as np
 
 BASES = "ACGT"
+_LETTERS = np.frombuffer(b"ACGTN", dtype=np.uint8)
 
 
 def to_text(codes):
-    """Codes 0..3 as a string over A, C, G, T."""
-    return "".join(BASES[int(c)] for c in codes)
+    """Codes 0..3 as a string over A, C, G, T (4 as N)."""
+    return _LETTERS[np.asarray(codes, dtype=np.uint8)].tobytes().decode()
 
 
 def suffix_array_by_rotations(codes):
@@ -48,6 +51,19 @@ def sa_interval(sa, codes, pattern):
         return 0, 0
     assert rows == list(range(rows[0], rows[0] + len(rows)))  # contiguous
     return rows[0], len(rows)
+
+
+def sa_interval_sorted(sa, txt, p):
+    """The same (k, s) found by bisection over the sorted rows: txt is the
+    text followed by '$' (as a string), p the pattern (a string).  Rows in
+    suffix order are sorted by their first len(p) characters too, so the
+    rows starting with p are those between the two bisection points."""
+    L = len(p)
+    rows = range(len(sa))
+    key = lambda i: txt[sa[i]:sa[i] + L]  # noqa: E731
+    lo = bisect.bisect_left(rows, p, key=key)
+    hi = bisect.bisect_right(rows, p, key=key)
+    return (lo, hi - lo) if hi > lo else (0, 0)
 
 
 def lookup(sa, intervals):

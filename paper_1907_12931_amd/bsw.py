@@ -70,6 +70,15 @@ SEED_RESULT_DTYPE = np.dtype([("score", "<i4"), ("qbeg", "<i4"), ("qend", "<i4")
 END_LOCAL, END_READ, END_NONE = 0, 1, 2
 # suffix-array lookup (bsw_sa_interval): rows [k, k + s)
 SA_INTERVAL_DTYPE = np.dtype([("k", "<u8"), ("s", "<u8")])
+# FM-index (bsw_fm_entry, bsw_bi_interval)
+FM_ENTRY_DTYPE = np.dtype([("count", "<u4", (4,)), ("bwt", "u1", (32,)), ("pad_", "u1", (16,))])
+BI_INTERVAL_DTYPE = np.dtype([("k", "<u8"), ("l", "<u8"), ("s", "<u8"), ("matched", "<i4"),
+                              ("pad_", "<i4")])
+
+
+class FmMeta(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_uint64), ("C", ctypes.c_uint64 * 4),
+                ("primary", ctypes.c_uint64), ("entries", ctypes.c_uint64)]
 
 _lib = None
 _VP = ctypes.c_void_p
@@ -137,6 +146,12 @@ def lib():
         L.bsw_sa_lookup_device.argtypes = [
             _VP, _VP, ctypes.c_uint64, _VP, ctypes.c_int64, _VP, _VP, ctypes.c_uint64,
             ctypes.POINTER(ctypes.c_uint64), _VP, ctypes.c_int32]
+        L.bsw_fm_build.restype = ctypes.c_int
+        L.bsw_fm_build.argtypes = [_VP, ctypes.c_uint64, _VP, _VP, ctypes.POINTER(FmMeta)]
+        L.bsw_fm_backward_search_device.restype = ctypes.c_int
+        L.bsw_fm_backward_search_device.argtypes = [
+            _VP, _VP, ctypes.POINTER(FmMeta), _VP, _VP, ctypes.c_int64, _VP, _VP,
+            ctypes.c_int32]
         L.bsw_ctx_tune_info.restype = ctypes.c_int
         L.bsw_ctx_tune_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
         L.bsw_server_create.restype = ctypes.c_int
@@ -306,6 +321,19 @@ class Context:
             1 if async_ else 0))
         return None if async_ else tot.value
 
+    def fm_backward_search_device(self, entries, meta, pat, pat_off, out, stream=None,
+                                  async_=False):
+        """Backward search (``bsw_fm_backward_search_device``): entries the
+        index (a GPU tensor of meta.entries * 64 bytes), pat a uint8 tensor,
+        pat_off an int64 tensor of n + 1 offsets, out a tensor of n * 32
+        bytes (BI_INTERVAL_DTYPE records)."""
+        n = pat_off.numel() - 1
+        s = stream.cuda_stream if stream is not None else None
+        _check(lib().bsw_fm_backward_search_device(
+            self._h, entries.data_ptr(), ctypes.byref(meta),
+            pat.data_ptr() if pat.numel() else None, pat_off.data_ptr(), n, out.data_ptr(),
+            s, 1 if async_ else 0))
+
     def last_cells(self):
         """Band cells settled by the last completed call (all its passes)."""
         v = ctypes.c_int64(0)
@@ -361,6 +389,19 @@ def to_device(batch, device="cuda"):
                 a = a.view(np.int64)
             dev[k] = torch.from_numpy(a).to(device)
     return dev
+
+
+def fm_build(text, sa):
+    """The FM-index of a text (codes 0..3) from its suffix array
+    (``bsw_fm_build``, host memory): (entries, FmMeta)."""
+    text = np.ascontiguousarray(text, dtype=np.uint8)
+    sa = np.ascontiguousarray(sa, dtype=np.int64)
+    rows = len(text) + 1
+    entries = np.zeros((rows + 31) // 32, dtype=FM_ENTRY_DTYPE)
+    meta = FmMeta()
+    _check(lib().bsw_fm_build(_ptr(text), len(text), sa.ctypes.data, entries.ctypes.data,
+                              ctypes.byref(meta)))
+    return entries, meta
 
 
 def seeds_to_device(reads, read_off, ref, seeds, device="cuda", with_ref_rev=False):

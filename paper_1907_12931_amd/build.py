@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsw.so")
 SOURCES = ["bsw_kernels.hip", "bsw_seed_kernels.hip", "bsw_sal_kernels.hip", "bsw_host.cpp",
-           "bsw_server.cpp", "bsw_seeds.cpp", "bsw_sal.cpp"]
+           "bsw_fm_kernels.hip", "bsw_server.cpp", "bsw_seeds.cpp", "bsw_sal.cpp",
+           "bsw_fm.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

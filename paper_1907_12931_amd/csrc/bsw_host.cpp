@@ -223,6 +223,7 @@ struct bsw_ctx {
   int (*pending_done)(bsw_ctx*) = nullptr;  // completion check of that call
   SeedState* seed = nullptr;                // read-level seed driver
   SalState* sal = nullptr;                  // suffix-array lookup
+  FmState* fm = nullptr;                    // FM-index search
   bool graph_call = false;  // the last call ran as a graph replay
   Status* last_st = nullptr;  // device status block of the last call
   double timing[4] = {0, 0, 0, 0};
@@ -811,6 +812,8 @@ SeedState*& ctx_seed_state(bsw_ctx* c) { return c->seed; }
 
 SalState*& ctx_sal_state(bsw_ctx* c) { return c->sal; }
 
+FmState*& ctx_fm_state(bsw_ctx* c) { return c->fm; }
+
 void ctx_set_kind(bsw_ctx* c, int kind) { c->kind = kind; }
 
 int ctx_tune_shapes(bsw_ctx* c, int kind, int n_params, int reps,
@@ -920,6 +923,7 @@ void bsw_ctx_destroy(bsw_ctx* c) {
   if (c->pending) (void)hipStreamSynchronize(c->pending_stream);
   seed_state_free(c->seed);
   sal_state_free(c->sal);
+  fm_state_free(c->fm);
   c->ws.release();
   c->in.release();
   c->res.release();

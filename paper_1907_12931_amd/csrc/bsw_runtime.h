@@ -137,6 +137,10 @@ void seed_state_free(SeedState* s);
 struct SalState;
 SalState*& ctx_sal_state(bsw_ctx* c);
 void sal_state_free(SalState* s);
+// State of the FM-index search, likewise.
+struct FmState;
+FmState*& ctx_fm_state(bsw_ctx* c);
+void fm_state_free(FmState* s);
 
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,

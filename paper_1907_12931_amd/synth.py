@@ -541,9 +541,27 @@ def sa_workload(ref_len=1 << 14, n_iv=2000, seed=6, **kw):
     return {"ref": ref, "text": text, "sa": sa, "iv": iv, "pattern_pos": p, "pattern_len": L}
 
 
+def fm_patterns(text, n, seed, length=(32, 32), p_sub=0.02, p_n=0.005):
+    """n search patterns from the forward half of a two-strand text: a
+    substring of length U[length] at a uniform position, with substitutions
+    at rate p_sub and N at rate p_n (a stand-in for read stretches)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    half = len(text) // 2
+    L = rng.integers(length[0], length[1] + 1, size=n)
+    off = _offsets(L)
+    p = rng.integers(0, max(1, half - length[1]), size=n)
+    idx = np.repeat(p, L) + (np.arange(int(L.sum())) - np.repeat(off[:-1].astype(np.int64), L))
+    pat = np.asarray(text, dtype=np.uint8)[idx].copy()
+    sub = rng.random(len(pat)) < p_sub
+    pat[sub] = (pat[sub] + rng.integers(1, 4, size=int(sub.sum()), dtype=np.uint8)) % 4
+    return _sprinkle_n(rng, pat, p_n), off
+
+
 # the lookup's benchmark workload: a 32 Mbase reference (64 Mbase indexed
 # text, a 512 MB suffix array) and 4 M intervals
 SA_BENCH = dict(ref_len=1 << 25, n_iv=4_000_000, seed=6)
+# the backward search's benchmark patterns over the same text: 4 M of 32 bases
+FM_BENCH_PATTERNS = 4_000_000
 
 
 # the read-level driver's benchmark workload: 500,000 reads of 151 bases

@@ -99,3 +99,18 @@ def test_generator_intervals_match_the_definition():
         assert (int(w["iv"][m]["k"]), int(w["iv"][m]["s"])) == (k, s)
     # repeats give intervals of more than one row
     assert (w["iv"]["s"] > 1).any()
+
+
+def test_bisection_interval_equals_row_by_row():
+    rng = np.random.default_rng(40)
+    for n in (1, 7, 60, 300):
+        r = rng.integers(0, 4 if n % 2 else 2, n).astype(np.uint8)
+        S = sal.suffix_array_by_rotations(r)
+        txt = sal.to_text(r) + "$"
+        for _ in range(30):
+            L = int(rng.integers(1, 7))
+            pat = rng.integers(0, 4, L).astype(np.uint8)
+            if rng.random() < 0.6 and n >= L:
+                p = int(rng.integers(0, n - L + 1))
+                pat = r[p:p + L]
+            assert sal.sa_interval_sorted(S, txt, sal.to_text(pat)) == sal.sa_interval(S, r, pat)
