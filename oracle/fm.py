@@ -76,3 +76,40 @@ def backward_search(text, sa, pattern, txt=None):
     l, s2 = sal.sa_interval_sorted(sa, txt, sal.to_text(revcomp(p)))
     assert s2 == s
     return k, l, s, matched
+
+
+def smems(text, sa, read, txt=None):
+    """Super-maximal exact matches of a read (Sec. 2.3, SMEM): with e(a) the
+    end of the longest substring starting at a that occurs in T, [a, e(a))
+    is a maximal exact match when it is not empty and cannot grow to the
+    left (e(a - 1) < e(a)), and it is super-maximal when no match starting
+    further left reaches as far (e(a) above every earlier e).  e is
+    non-decreasing, so one sweep finds it.  Returns (start, end, k, l, s)
+    tuples in order of start."""
+    x = np.asarray(read, dtype=np.uint8)
+    if txt is None:
+        txt = sal.to_text(text) + "$"
+    n = len(x)
+
+    def occurs(a, b):
+        return (x[a:b] < 4).all() and sal.sa_interval_sorted(sa, txt, sal.to_text(x[a:b]))[1] > 0
+
+    out = []
+    best = 0  # largest e so far
+    b = 0
+    for a in range(n):
+        b = max(b, a)
+        while b < n and occurs(a, b + 1):
+            b += 1
+        if b > a and b > best:
+            k, l, s = bi_interval_sorted(sa, txt, x[a:b])
+            out.append((a, b, k, l, s))
+        best = max(best, b)
+    return out
+
+
+def bi_interval_sorted(sa, txt, x):
+    k, s = sal.sa_interval_sorted(sa, txt, sal.to_text(x))
+    l, s2 = sal.sa_interval_sorted(sa, txt, sal.to_text(revcomp(x)))
+    assert s == s2
+    return k, l, s

@@ -91,3 +91,30 @@ def test_backward_search_matched_length():
         want = max(j for j in range(len(q) + 1) if sal.to_text(q[len(q) - j:]) in txt)
         assert m == want
         assert (s > 0) == (m == len(q))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_smems_by_brute_force(seed):
+    """Every occurring substring of the read is listed; the MEMs are those
+    that occur and cannot grow by one base on either side, the SMEMs the
+    MEMs no other MEM contains."""
+    rng = np.random.default_rng(50 + seed)
+    t = both_strands(rng, int(rng.integers(20, 70)), 2 if seed == 0 else 4)
+    S = sal.suffix_array_by_rotations(t)
+    txt = sal.to_text(t)
+    for _ in range(15):
+        p = int(rng.integers(0, len(t) - 20))
+        x = t[p:p + int(rng.integers(1, 20))].copy()
+        for j in rng.integers(0, len(x), int(rng.integers(0, 3))):
+            x[j] = int(rng.integers(0, 5))
+        xs = sal.to_text(x)
+        occ = lambda a, b: a < b and "N" not in xs[a:b] and xs[a:b] in txt  # noqa: E731
+        mems = [(a, b) for a in range(len(x)) for b in range(a + 1, len(x) + 1)
+                if occ(a, b) and not (a > 0 and occ(a - 1, b))
+                and not (b < len(x) and occ(a, b + 1))]
+        want = sorted((a, b) for a, b in mems
+                      if not any(c <= a and b <= d and (c, d) != (a, b) for c, d in mems))
+        got = fm.smems(t, S, x)
+        assert [(a, b) for a, b, *_ in got] == want
+        for a, b, k, l, s in got:
+            assert (k, l, s) == fm.bi_interval(t, S, x[a:b])
