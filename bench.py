@@ -311,6 +311,75 @@ def fm_search(bsw, synth, torch, np, w, steps, warmup):
                          "alg_bytes_per_launch": alg}}
 
 
+def smem_reads(synth, w):
+    return synth.fm_patterns(w["text"], synth.SMEM_BENCH_READS, seed=54, length=(151, 151),
+                             p_sub=0.02, p_n=0.005)
+
+
+def smem_search(bsw, synth, torch, np, w, steps, warmup):
+    """SMEMs of the benchmark reads over the FM index of the lookup's
+    two-strand text."""
+    entries, meta = bsw.fm_build(w["text"], w["sa"])
+    reads, off = smem_reads(synth, w)
+    n = len(off) - 1
+    E = torch.from_numpy(entries.view(np.uint8)).cuda()
+    rd = torch.from_numpy(reads).cuda()
+    od = torch.from_numpy(off.astype(np.uint64).view(np.int64)).cuda()
+    out = torch.empty(len(reads) * bsw.SMEM_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    counts = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx = bsw.Context()
+    for _ in range(max(1, warmup)):
+        ctx.fm_smem_device(E, meta, rd, od, 151, out, counts)
+    torch.cuda.synchronize()
+    ms = []
+    t = time.perf_counter()
+    for _ in range(steps):
+        ctx.fm_smem_device(E, meta, rd, od, 151, out, counts)
+        ms.append(ctx.last_timing()[0])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / steps
+    ext = ctx.last_cells()
+    ctx.close()
+    n_smem = int(counts.sum().item())
+    kms = float(np.mean(ms))
+    alg = 2 * 64 * ext  # two 64-byte entries read per extension step
+    gbs = alg / (kms / 1e3) / 1e9
+    return {"value": round(n / wall, 1), "unit": "reads/s",
+            "smems_per_s": round(n_smem / wall, 1), "extensions_per_s": round(ext / wall, 1),
+            "ms_per_step": round(wall * 1e3, 3), "kernel_ms": round(kms, 3), "reads": n,
+            "smems": n_smem, "extension_steps": int(ext),
+            "workload": f"{n} reads of 151 bases from the {len(w['ref'])}-base reference "
+                        "(2% substitutions, 0.5% N) against the FM index of it and its "
+                        f"reverse complement ({len(w['sa'])} rows)",
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": None, "kernel": "bsw::k_fm_smem",
+                         "alg_bytes_per_launch": alg}}
+
+
+def smem_cpu_baseline(np, synth, w, seconds):
+    """The reference SMEMs on the host, on a random sample of the benchmark
+    reads sized for about `seconds` of work."""
+    from oracle import fm, sal
+    reads, off = smem_reads(synth, w)
+    txt = sal.to_text(w["text"]) + "$"
+    rng = np.random.default_rng(0)
+    n = len(off) - 1
+
+    def run(m):
+        idx = rng.choice(n, size=m, replace=False)
+        t = time.perf_counter()
+        for j in idx:
+            fm.smems(w["text"], w["sa"], reads[off[j]:off[j + 1]], txt)
+        return time.perf_counter() - t
+
+    dt0 = run(50)
+    m = int(min(n, max(50, 50 / dt0 * seconds)))
+    dt = run(m)
+    return {"value": round(m / dt, 1), "unit": "reads/s", "cores": 1, "kind": "oracle",
+            "sample": f"{m} random reads of the {n}, {dt:.1f} s"}
+
+
 def fm_cpu_baseline(np, synth, w, seconds):
     """The reference backward search on the host, on a random sample of the
     benchmark patterns sized for about `seconds` of work."""
@@ -373,6 +442,8 @@ def main():
     ap.add_argument("--fm-only", action="store_true",
                     help="run only the FM-index backward search leg and print it as the "
                          "JSON line")
+    ap.add_argument("--smem-only", action="store_true",
+                    help="run only the SMEM search leg and print it as the JSON line")
     ap.add_argument("--seeds-only", action="store_true",
                     help="run only the seed driver leg and print it as the JSON line "
                          "(for profiling it alone)")
@@ -403,6 +474,13 @@ def main():
         torch.cuda.synchronize()
         del x, y
     workers = min(16, os.cpu_count() or 1)
+    if args.smem_only:
+        w = synth.sa_workload(**synth.SA_BENCH)
+        leg = smem_search(bsw, synth, torch, np, w, args.steps, args.warmup)
+        if not args.no_cpu:
+            leg["cpu_baseline"] = smem_cpu_baseline(np, synth, w, args.cpu_seconds)
+        print(json.dumps(leg), flush=True)
+        return
     if args.fm_only:
         w = synth.sa_workload(**synth.SA_BENCH)
         leg = fm_search(bsw, synth, torch, np, w, args.steps, args.warmup)
@@ -502,8 +580,10 @@ def main():
         log(f"sa lookup: {sal_leg}")
         fm_leg = fm_search(bsw, synth, torch, np, sal_w, args.steps, args.warmup)
         log(f"fm search: {fm_leg}")
+        smem_leg = smem_search(bsw, synth, torch, np, sal_w, args.steps, args.warmup)
+        log(f"smem search: {smem_leg}")
     else:
-        fm_leg = None
+        fm_leg = smem_leg = None
 
     seeds_leg = None
     if not args.no_seeds:
@@ -561,6 +641,8 @@ def main():
             log(f"cpu sa lookup: {sal_leg['cpu_baseline']}")
             fm_leg["cpu_baseline"] = fm_cpu_baseline(np, synth, sal_w, args.cpu_seconds)
             log(f"cpu fm search: {fm_leg['cpu_baseline']}")
+            smem_leg["cpu_baseline"] = smem_cpu_baseline(np, synth, sal_w, args.cpu_seconds)
+            log(f"cpu smem search: {smem_leg['cpu_baseline']}")
 
     res = {
         "metric": "GCUPS (bit-exact vs oracle) batched vs plain; p50/p99 latency under serving",
@@ -575,7 +657,7 @@ def main():
                    "dp_launches": b["dp_launches"], "graph": True, "tuned": tuned,
                    "prep_bin_ms": round(p["prep_ms"], 3)},
         "plain": plain, "serving": serving, "seed_driver": seeds_leg, "sa_lookup": sal_leg,
-        "fm_search": fm_leg,
+        "fm_search": fm_leg, "smem_search": smem_leg,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

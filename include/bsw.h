@@ -460,6 +460,36 @@ int bsw_fm_backward_search_device(bsw_ctx* ctx, const bsw_fm_entry* entries,
                                   const uint64_t* pat_off, int64_t n, bsw_bi_interval* out,
                                   void* stream, int32_t async);
 
+/* One SMEM of a read (32 bytes): read[start, end) occurs in T at the rows
+ * of its bi-interval (k, l, s). */
+typedef struct bsw_smem {
+  uint32_t start, end;
+  uint64_t k, l, s;
+} bsw_smem;
+
+/* Super-maximal exact matches (Sec. 2.3 SMEM step; Algorithms 3 and 4) of
+ * n_reads reads against the index (device memory; meta host memory): read
+ * r is reads[read_off[r] .. read_off[r + 1]), codes 0..4, at most max_len
+ * bases.  For pivot x = 0, the matches through x are found by extending
+ * X[x] forward while it occurs (keeping the bi-interval each time the
+ * number of occurrences changes), then extending those backward, longest
+ * first; a match that stops growing to the left and is contained in no
+ * longer one is an SMEM.  The next pivot is the end of the longest forward
+ * match (a pivot on an N moves on by one).  Every SMEM of a read is found
+ * once.  The SMEMs of read r, in order of start, go to
+ * out[read_off[r] - read_off[0] ...] (out has room for as many entries as
+ * the reads have bases) and their number to counts[r].  A read longer than
+ * max_len, offsets out of order or a code > 4 fail the call with nothing
+ * written.  Arena use: 48 * max_len bytes per lane of a fixed grid of
+ * 131,072 lanes (about 7 MB per base of max_len).  bsw_ctx_last_timing [0]
+ * = the search kernel; bsw_ctx_last_cells = the extension steps run (two
+ * index entries read each).  stream and async as for
+ * bsw_extend_batch_device. */
+int bsw_fm_smem_device(bsw_ctx* ctx, const bsw_fm_entry* entries, const bsw_fm_meta* meta,
+                       const uint8_t* reads, const uint64_t* read_off, int64_t n_reads,
+                       uint32_t max_len, bsw_smem* out, int32_t* counts, void* stream,
+                       int32_t async);
+
 /* Text of the calling thread's most recent error ("" if none). */
 const char* bsw_last_error(void);
 

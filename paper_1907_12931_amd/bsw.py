@@ -74,6 +74,8 @@ SA_INTERVAL_DTYPE = np.dtype([("k", "<u8"), ("s", "<u8")])
 FM_ENTRY_DTYPE = np.dtype([("count", "<u4", (4,)), ("bwt", "u1", (32,)), ("pad_", "u1", (16,))])
 BI_INTERVAL_DTYPE = np.dtype([("k", "<u8"), ("l", "<u8"), ("s", "<u8"), ("matched", "<i4"),
                               ("pad_", "<i4")])
+SMEM_DTYPE = np.dtype([("start", "<u4"), ("end", "<u4"), ("k", "<u8"), ("l", "<u8"),
+                       ("s", "<u8")])
 
 
 class FmMeta(ctypes.Structure):
@@ -152,6 +154,10 @@ def lib():
         L.bsw_fm_backward_search_device.argtypes = [
             _VP, _VP, ctypes.POINTER(FmMeta), _VP, _VP, ctypes.c_int64, _VP, _VP,
             ctypes.c_int32]
+        L.bsw_fm_smem_device.restype = ctypes.c_int
+        L.bsw_fm_smem_device.argtypes = [_VP, _VP, ctypes.POINTER(FmMeta), _VP, _VP,
+                                         ctypes.c_int64, ctypes.c_uint32, _VP, _VP, _VP,
+                                         ctypes.c_int32]
         L.bsw_ctx_tune_info.restype = ctypes.c_int
         L.bsw_ctx_tune_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
         L.bsw_server_create.restype = ctypes.c_int
@@ -333,6 +339,19 @@ class Context:
             self._h, entries.data_ptr(), ctypes.byref(meta),
             pat.data_ptr() if pat.numel() else None, pat_off.data_ptr(), n, out.data_ptr(),
             s, 1 if async_ else 0))
+
+    def fm_smem_device(self, entries, meta, reads, read_off, max_len, out, counts,
+                       stream=None, async_=False):
+        """SMEMs of every read (``bsw_fm_smem_device``): reads a uint8 tensor,
+        read_off int64 (n + 1), out a tensor of (read bases) * 32 bytes
+        (SMEM_DTYPE records, read r's at its own offset), counts int32 (n)."""
+        n = read_off.numel() - 1
+        s = stream.cuda_stream if stream is not None else None
+        _check(lib().bsw_fm_smem_device(
+            self._h, entries.data_ptr(), ctypes.byref(meta),
+            reads.data_ptr() if reads.numel() else None, read_off.data_ptr(), n, max_len,
+            out.data_ptr() if out.numel() else None, counts.data_ptr(), s,
+            1 if async_ else 0))
 
     def last_cells(self):
         """Band cells settled by the last completed call (all its passes)."""

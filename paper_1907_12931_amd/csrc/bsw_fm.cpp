@@ -14,8 +14,18 @@ void launch_fm_search(const bsw_fm_entry* E, const bsw_fm_meta& meta, const uint
                       const uint64_t* off, int64_t n, const Status* st, bsw_bi_interval* out,
                       hipStream_t s);
 
+void launch_smem_check(const uint64_t* off, int64_t n, uint32_t cap, Status* st,
+                       hipStream_t s);
+size_t smem_list_entry_bytes();
+void launch_fm_smem(const bsw_fm_entry* E, const bsw_fm_meta& meta, const uint8_t* reads,
+                    const uint64_t* off, int64_t n, uint32_t cap, void* scratch,
+                    unsigned blocks, Status* st, bsw_smem* out, int32_t* counts,
+                    hipStream_t s);
+
+constexpr unsigned SMEM_BLOCKS = 512;  // 131,072 lanes, each with its own list slot
+
 struct FmState {
-  DevBuf ws;               // status block
+  DevBuf ws;               // status block, list scratch
   Status* h_st = nullptr;  // pinned copy
   hipEvent_t ev[2] = {};   // search start, end
 };
@@ -65,10 +75,10 @@ int fm_state(bsw_ctx* c, FmState** out) {
   return BSW_OK;
 }
 
-int fm_done(bsw_ctx* c) {
+int fm_finish(bsw_ctx* c, const char* what) {
   FmState* S = ctx_fm_state(c);
   if (S->h_st->bad)
-    return set_error(BSW_EINVAL, "pattern %llu: offsets out of order or a code > 4",
+    return set_error(BSW_EINVAL, "%s %llu: offsets out of order, too long or a code > 4", what,
                      ~(unsigned long long)S->h_st->first_bad_inv);
   float ms = 0;
   if (hipEventElapsedTime(&ms, S->ev[0], S->ev[1]) != hipSuccess) {
@@ -78,7 +88,20 @@ int fm_done(bsw_ctx* c) {
   double* t = ctx_timing(c);
   t[0] = ms;
   t[1] = t[2] = t[3] = 0;
-  ctx_set_cells(c, 0);
+  ctx_set_cells(c, S->h_st->cls_cells[0]);
+  return BSW_OK;
+}
+
+int fm_done(bsw_ctx* c) { return fm_finish(c, "pattern"); }
+int smem_done(bsw_ctx* c) { return fm_finish(c, "read"); }
+
+int check_meta(const bsw_fm_meta* meta) {
+  if (meta->rows < 1 || meta->entries != (meta->rows + BSW_FM_ETA - 1) / BSW_FM_ETA ||
+      meta->primary >= meta->rows || meta->C[0] != 1 || meta->rows > 0xffffffffull)
+    return set_error(BSW_EINVAL, "meta does not describe an index built by bsw_fm_build");
+  for (int k = 1; k < 4; ++k)
+    if (meta->C[k] < meta->C[k - 1] || meta->C[k] > meta->rows)
+      return set_error(BSW_EINVAL, "meta does not describe an index built by bsw_fm_build");
   return BSW_OK;
 }
 
@@ -141,13 +164,9 @@ int bsw_fm_backward_search_device(bsw_ctx* c, const bsw_fm_entry* E, const bsw_f
   if (n == 0) return BSW_OK;
   if (!E || !meta || !pat_off || !out)
     return set_error(BSW_EINVAL, "a required pointer is NULL");
-  if (meta->rows < 1 || meta->entries != (meta->rows + BSW_FM_ETA - 1) / BSW_FM_ETA ||
-      meta->primary >= meta->rows || meta->C[0] != 1)
-    return set_error(BSW_EINVAL, "meta does not describe an index built by bsw_fm_build");
-  for (int k = 1; k < 4; ++k)
-    if (meta->C[k] < meta->C[k - 1] || meta->C[k] > meta->rows)
-      return set_error(BSW_EINVAL, "meta does not describe an index built by bsw_fm_build");
-  int rc = ctx_set_device(c);
+  int rc = check_meta(meta);
+  if (rc) return rc;
+  if ((rc = ctx_set_device(c))) return rc;
   if (rc) return rc;
   FmState* S;
   if ((rc = fm_state(c, &S))) return rc;
@@ -168,6 +187,45 @@ int bsw_fm_backward_search_device(bsw_ctx* c, const bsw_fm_entry* E, const bsw_f
   }
   HIPCHK(hipStreamSynchronize(s));
   return fm_done(c);
+}
+
+int bsw_fm_smem_device(bsw_ctx* c, const bsw_fm_entry* E, const bsw_fm_meta* meta,
+                       const uint8_t* reads, const uint64_t* read_off, int64_t n,
+                       uint32_t max_len, bsw_smem* out, int32_t* counts, void* stream,
+                       int32_t async) {
+  if (!c) return set_error(BSW_EINVAL, "ctx is NULL");
+  if (n < 0 || n > 0x7fffffffLL)
+    return set_error(BSW_EINVAL, "n_reads = %lld out of range", (long long)n);
+  if (n == 0) return BSW_OK;
+  if (!E || !meta || !read_off || !counts || (max_len && (!reads || !out)))
+    return set_error(BSW_EINVAL, "a required pointer is NULL");
+  if (max_len > BSW_MAX_LEN) return set_error(BSW_EINVAL, "max_len above %d", BSW_MAX_LEN);
+  int rc = check_meta(meta);
+  if (rc) return rc;
+  if ((rc = ctx_set_device(c))) return rc;
+  FmState* S;
+  if ((rc = fm_state(c, &S))) return rc;
+  const size_t lanes = (size_t)SMEM_BLOCKS * 256;
+  const size_t cap = max_len ? max_len : 1;
+  const size_t o_scr = (sizeof(Status) + 255) / 256 * 256;  // lists after the status
+  if ((rc = S->ws.ensure(o_scr + lanes * 2 * cap * smem_list_entry_bytes()))) return rc;
+  Status* st = (Status*)S->ws.p;
+  hipStream_t s = stream ? (hipStream_t)stream : ctx_stream(c);
+  launch_fill((uint32_t*)st, (int64_t)(sizeof(Status) / 4), s);
+  launch_smem_check(read_off, n, max_len, st, s);
+  if (reads) launch_codes(reads, read_off, n, st, 0, s);
+  HIPCHK(hipEventRecord(S->ev[0], s));
+  launch_fm_smem(E, *meta, reads, read_off, n, (uint32_t)cap, (char*)S->ws.p + o_scr,
+                 SMEM_BLOCKS, st, out, counts, s);
+  HIPCHK(hipEventRecord(S->ev[1], s));
+  HIPCHK(hipMemcpyAsync(S->h_st, st, sizeof(Status), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipGetLastError());
+  if (async) {
+    ctx_set_pending(c, s, smem_done);
+    return BSW_OK;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return smem_done(c);
 }
 
 }  // extern "C"

@@ -7,48 +7,18 @@
 // many-queries-at-once form that Sec. 4.3 tried on the CPU).
 //   k_fm_check   per pattern: its offsets are ordered
 //   k_fm_search  the search, one pattern per lane
+//   k_smem_check per read: offsets ordered, length within the list capacity
+//   k_fm_smem    the SMEMs of every read (Algorithms 3 and 4 around each
+//                pivot, the pivot moving to the end of the longest forward
+//                match), one read per lane, the interval lists of a lane in
+//                its own slot of scratch memory
 #include <hip/hip_runtime.h>
 
 #include "../../include/bsw.h"
+#include "bsw_fm_device.h"
 #include "bsw_internal.h"
 
 namespace bsw {
-
-namespace {
-
-// O(c, t) for the four bases at once (Algorithm 1): the entry's counts plus
-// the occurrences among its first t % 32 + 1 symbols.  A byte of x is zero
-// exactly when ((x & 0x7f) + 0x7f) | x has its top bit clear (no carry
-// crosses bytes), so each dword yields exact per-byte matches.
-__device__ __forceinline__ void occ4(const bsw_fm_entry* __restrict__ E, int64_t t,
-                                     uint32_t o[4]) {
-  if (t < 0) {
-    o[0] = o[1] = o[2] = o[3] = 0;
-    return;
-  }
-  const uint4* p = (const uint4*)(E + (t >> 5));
-  const uint4 cnt = p[0], b0 = p[1], b1 = p[2];
-  const uint32_t w[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-  const int y = (int)(t & 31);
-  uint32_t n[4] = {0, 0, 0, 0};
-#pragma unroll
-  for (int d = 0; d < 8; ++d) {
-    const int r = y - 4 * d;  // last byte of this dword that is counted
-    const uint32_t keep = r < 0 ? 0u : (r >= 3 ? 0x80808080u : 0x80808080u >> (8 * (3 - r)));
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const uint32_t x = w[d] ^ (0x01010101u * (uint32_t)c);
-      const uint32_t nonzero = (((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) & 0x80808080u;
-      n[c] += (uint32_t)__popc(~nonzero & keep);
-    }
-  }
-  o[0] = cnt.x + n[0];
-  o[1] = cnt.y + n[1];
-  o[2] = cnt.z + n[2];
-  o[3] = cnt.w + n[3];
-}
-
-}  // namespace
 
 __global__ void __launch_bounds__(256)
 k_fm_check(const uint64_t* __restrict__ off, int64_t n, Status* st) {
@@ -73,21 +43,12 @@ k_fm_search(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
     for (uint64_t i = q1; i > q0; --i) {
       const uint32_t c = pat[i - 1];
       if (c > 3) break;
-      uint32_t lo[4], hi[4];
-      occ4(E, (int64_t)k - 1, lo);
-      occ4(E, (int64_t)(k + s) - 1, hi);
-      uint64_t sz[4];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) sz[d] = hi[d] - lo[d];
-      if (sz[c] == 0) break;
-      // the reverse complement's rows: after the row ending in $ (when the
-      // interval holds the whole text's row) come the extensions by T, G,
-      // C, A of X's complement, i.e. by A, C, G, T of the reverse
-      uint64_t nl = l + (k <= meta.primary && meta.primary < k + s ? 1 : 0);
-      for (int d = 3; d > (int)c; --d) nl += sz[d];
-      k = meta.C[c] + lo[c];
-      l = nl;
-      s = sz[c];
+      uint64_t k2, l2, s2;
+      back_ext(E, meta, k, l, s, c, k2, l2, s2);
+      if (s2 == 0) break;
+      k = k2;
+      l = l2;
+      s = s2;
       ++matched;
     }
     bsw_bi_interval r;
@@ -99,6 +60,149 @@ k_fm_search(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
     r.pad_ = 0;
     out[m] = r;
   }
+}
+
+__global__ void __launch_bounds__(256)
+k_smem_check(const uint64_t* __restrict__ off, int64_t n, uint32_t cap, Status* st) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n; m += stride)
+    if (off[m + 1] < off[m] || off[m + 1] - off[m] > cap) {
+      atomicMax(&st->first_bad_inv, ~(unsigned long long)m);
+      atomicOr(&st->bad, 1u);
+    }
+}
+
+namespace {
+struct ListEnt {  // a bi-interval and the read end of its match
+  uint64_t k, l;
+  uint32_t s, end;
+};
+}  // namespace
+
+// Per read: pivot x = 0; the SMEMs through x are found by extending X[x]
+// forward while it occurs, keeping the bi-interval each time its size
+// changes (the matches X[x, e) for every e where the occurrences change),
+// then extending those matches backward base by base, longest first: a match
+// that cannot grow to the left is a maximal match starting at the current
+// position, super-maximal when no longer match failed at the same position
+// and no match already kept starts there; among matches whose extensions
+// have equal sizes only the longest is kept.  The next pivot is the end of
+// the longest forward match.  Output: the read's SMEMs in order of start at
+// out[off[r] - off[0] ...], their number in counts[r]; steps counts the
+// extension steps (two index entries read each).
+__global__ void __launch_bounds__(256)
+k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
+          const uint8_t* __restrict__ reads, const uint64_t* __restrict__ off, int64_t n,
+          uint32_t cap, ListEnt* __restrict__ scratch, Status* st, bsw_smem* __restrict__ out,
+          int32_t* __restrict__ counts) {
+  if (st->bad) return;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t G = (int64_t)gridDim.x * blockDim.x;
+  ListEnt* bufA = scratch + (size_t)g * 2 * cap;
+  ListEnt* bufB = bufA + cap;
+  const uint64_t base = off[0];
+  unsigned long long steps = 0;  // this lane's extension steps
+  for (int64_t r = g; r < n; r += G) {
+    const uint8_t* X = reads + off[r];
+    const int L = (int)(off[r + 1] - off[r]);
+    bsw_smem* o = out + (off[r] - base);
+    int cnt = 0;
+    int x = 0;
+    while (x < L) {
+      uint32_t c = X[x];
+      if (c > 3) {
+        ++x;
+        continue;
+      }
+      // forward (Algorithm 3) from the single base at x
+      uint64_t k = meta.C[c], l = meta.C[3 - c];
+      uint64_t s = (c < 3 ? meta.C[c + 1] : meta.rows) - meta.C[c];
+      uint32_t end = (uint32_t)x + 1;
+      ListEnt* cur = bufA;
+      int ncur = 0;
+      int i = x + 1;
+      for (; i < L; ++i) {
+        c = X[i];
+        if (c > 3) {
+          cur[ncur++] = {k, l, (uint32_t)s, end};
+          break;
+        }
+        uint64_t k2, l2, s2;
+        fwd_ext(E, meta, k, l, s, c, k2, l2, s2);
+        ++steps;
+        if (s2 != s) cur[ncur++] = {k, l, (uint32_t)s, end};
+        if (s2 == 0) break;
+        k = k2;
+        l = l2;
+        s = s2;
+        end = (uint32_t)i + 1;
+      }
+      if (i == L) cur[ncur++] = {k, l, (uint32_t)s, end};
+      const int next = (int)cur[ncur - 1].end;
+      // backward (Algorithm 4), longest forward match first
+      ListEnt* prev = bufB;
+      int nprev = ncur;
+      for (int j = 0; j < ncur; ++j) prev[j] = cur[ncur - 1 - j];
+      cur = bufA;
+      const int first = cnt;
+      for (int ii = x - 1;; --ii) {
+        const int cc = ii >= 0 && X[ii] < 4 ? (int)X[ii] : -1;
+        ncur = 0;
+        for (int j = 0; j < nprev; ++j) {
+          const ListEnt p = prev[j];
+          uint64_t k2 = 0, l2 = 0, s2 = 0;
+          if (cc >= 0) {
+            back_ext(E, meta, p.k, p.l, p.s, (uint32_t)cc, k2, l2, s2);
+            ++steps;
+          }
+          if (cc < 0 || s2 == 0) {
+            if (ncur == 0 && (cnt == first || ii + 1 < (int)o[cnt - 1].start) && cnt < L)
+              o[cnt++] = {(uint32_t)(ii + 1), p.end, p.k, p.l, (uint64_t)p.s};
+          } else if (ncur == 0 || (uint32_t)s2 != cur[ncur - 1].s) {
+            cur[ncur++] = {k2, l2, (uint32_t)s2, p.end};
+          }
+        }
+        if (ncur == 0) break;
+        ListEnt* t = prev;
+        prev = cur;
+        cur = t;
+        nprev = ncur;
+      }
+      // this pivot's SMEMs came out longest first, i.e. by decreasing start
+      for (int a = first, b = cnt - 1; a < b; ++a, --b) {
+        const bsw_smem t = o[a];
+        o[a] = o[b];
+        o[b] = t;
+      }
+      x = next;
+    }
+    counts[r] = cnt;
+  }
+  // one atomic per wave (every lane of the wave gets here)
+  for (int d = 32; d > 0; d >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)steps, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(steps >> 32), d, 64);
+    steps += ((unsigned long long)hi << 32) | lo;
+  }
+  if ((threadIdx.x & 63) == 0) atomicAdd(&st->cls_cells[0], steps);
+}
+
+void launch_smem_check(const uint64_t* off, int64_t n, uint32_t cap, Status* st,
+                       hipStream_t s) {
+  int64_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  hipLaunchKernelGGL(k_smem_check, dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, off, n,
+                     cap, st);
+}
+
+size_t smem_list_entry_bytes() { return sizeof(ListEnt); }
+
+void launch_fm_smem(const bsw_fm_entry* E, const bsw_fm_meta& meta, const uint8_t* reads,
+                    const uint64_t* off, int64_t n, uint32_t cap, void* scratch,
+                    unsigned blocks, Status* st, bsw_smem* out, int32_t* counts,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_fm_smem, dim3(blocks), dim3(256), 0, s, E, meta, reads, off, n, cap,
+                     (ListEnt*)scratch, st, out, counts);
 }
 
 void launch_fm_check(const uint64_t* off, int64_t n, Status* st, hipStream_t s) {

@@ -562,6 +562,8 @@ def fm_patterns(text, n, seed, length=(32, 32), p_sub=0.02, p_n=0.005):
 SA_BENCH = dict(ref_len=1 << 25, n_iv=4_000_000, seed=6)
 # the backward search's benchmark patterns over the same text: 4 M of 32 bases
 FM_BENCH_PATTERNS = 4_000_000
+# and the SMEM search's reads: 500,000 of 151 bases
+SMEM_BENCH_READS = 500_000
 
 
 # the read-level driver's benchmark workload: 500,000 reads of 151 bases

@@ -96,3 +96,40 @@ def test_seed_layouts_match_header(tmp_path):
         assert [dt.itemsize] + [dt.fields[f][1] for f in dt.names] == res
     assert (bsw.END_LOCAL, bsw.END_READ, bsw.END_NONE) == (
         oseeds.LOCAL, oseeds.READ_END, oseeds.NONE)
+
+
+def test_index_layouts_match_header(tmp_path):
+    """bsw_sa_interval, bsw_fm_entry, bsw_fm_meta, bsw_bi_interval and
+    bsw_smem as a C compiler lays them out equal the binding's types."""
+    import subprocess
+    from paper_1907_12931_amd import bsw, synth
+    src = tmp_path / "lay2.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "bsw.h"\nint main(void) {\n'
+        '  printf("%zu %zu %zu\\n", sizeof(bsw_sa_interval), offsetof(bsw_sa_interval, k),'
+        ' offsetof(bsw_sa_interval, s));\n'
+        '  printf("%zu %zu %zu %zu\\n", sizeof(bsw_fm_entry), offsetof(bsw_fm_entry, count),'
+        ' offsetof(bsw_fm_entry, bwt), offsetof(bsw_fm_entry, pad_));\n'
+        '  printf("%zu %zu %zu %zu %zu\\n", sizeof(bsw_fm_meta), offsetof(bsw_fm_meta, rows),'
+        ' offsetof(bsw_fm_meta, C), offsetof(bsw_fm_meta, primary), offsetof(bsw_fm_meta, entries));\n'
+        '  printf("%zu %zu %zu %zu %zu\\n", sizeof(bsw_bi_interval), offsetof(bsw_bi_interval, k),'
+        ' offsetof(bsw_bi_interval, l), offsetof(bsw_bi_interval, s), offsetof(bsw_bi_interval, matched));\n'
+        '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(bsw_smem), offsetof(bsw_smem, start),'
+        ' offsetof(bsw_smem, end), offsetof(bsw_smem, k), offsetof(bsw_smem, l), offsetof(bsw_smem, s));\n'
+        '  return 0;\n}\n')
+    exe = tmp_path / "lay2"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    rows = [[int(v) for v in line.split()] for line in
+            subprocess.run([str(exe)], check=True, capture_output=True,
+                           text=True).stdout.strip().split("\n")]
+
+    def lay(dt, names):
+        return [dt.itemsize] + [dt.fields[f][1] for f in names]
+
+    assert rows[0] == lay(bsw.SA_INTERVAL_DTYPE, ("k", "s")) == lay(synth.SA_INTERVAL, ("k", "s"))
+    assert rows[1] == lay(bsw.FM_ENTRY_DTYPE, ("count", "bwt", "pad_"))
+    assert rows[2] == [ctypes.sizeof(bsw.FmMeta), bsw.FmMeta.rows.offset, bsw.FmMeta.C.offset,
+                       bsw.FmMeta.primary.offset, bsw.FmMeta.entries.offset]
+    assert rows[3] == lay(bsw.BI_INTERVAL_DTYPE, ("k", "l", "s", "matched"))
+    assert rows[4] == lay(bsw.SMEM_DTYPE, ("start", "end", "k", "l", "s"))
