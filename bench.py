@@ -353,7 +353,8 @@ def smem_search(bsw, synth, torch, np, w, steps, warmup):
                         f"reverse complement ({len(w['sa'])} rows)",
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                         "traffic": None, "kernel": "bsw::k_fm_smem",
+                         "traffic": traffic_from_profile("bsw::k_fm_smem", alg, profile="fm"),
+                         "kernel": "bsw::k_fm_smem",
                          "alg_bytes_per_launch": alg}}
 
 
