@@ -480,8 +480,9 @@ typedef struct bsw_smem {
  * out[read_off[r] - read_off[0] ...] (out has room for as many entries as
  * the reads have bases) and their number to counts[r].  A read longer than
  * max_len, offsets out of order or a code > 4 fail the call with nothing
- * written.  Arena use: 48 * max_len bytes per lane of a fixed grid of
- * 131,072 lanes (about 7 MB per base of max_len).  bsw_ctx_last_timing [0]
+ * written.  One read per lane, with as many lanes as the device holds at
+ * once (at most one per read); arena use: 48 * max_len bytes per lane
+ * (about 2.4 GB for 151-base reads on a full MI355X).  bsw_ctx_last_timing [0]
  * = the search kernel; bsw_ctx_last_cells = the extension steps run (two
  * index entries read each).  stream and async as for
  * bsw_extend_batch_device. */

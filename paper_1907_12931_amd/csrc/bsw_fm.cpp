@@ -17,12 +17,12 @@ void launch_fm_search(const bsw_fm_entry* E, const bsw_fm_meta& meta, const uint
 void launch_smem_check(const uint64_t* off, int64_t n, uint32_t cap, Status* st,
                        hipStream_t s);
 size_t smem_list_entry_bytes();
+int fm_smem_blocks_per_cu();
 void launch_fm_smem(const bsw_fm_entry* E, const bsw_fm_meta& meta, const uint8_t* reads,
                     const uint64_t* off, int64_t n, uint32_t cap, void* scratch,
                     unsigned blocks, Status* st, bsw_smem* out, int32_t* counts,
                     hipStream_t s);
 
-constexpr unsigned SMEM_BLOCKS = 512;  // 131,072 lanes, each with its own list slot
 
 struct FmState {
   DevBuf ws;               // status block, list scratch
@@ -205,7 +205,11 @@ int bsw_fm_smem_device(bsw_ctx* c, const bsw_fm_entry* E, const bsw_fm_meta* met
   if ((rc = ctx_set_device(c))) return rc;
   FmState* S;
   if ((rc = fm_state(c, &S))) return rc;
-  const size_t lanes = (size_t)SMEM_BLOCKS * 256;
+  // as many lanes as can be resident at once (the search hides its latency
+  // with them), but no more than one per read; each has its own list slot
+  const size_t resident = (size_t)fm_smem_blocks_per_cu() * ctx_num_cu(c);
+  const size_t blocks = std::max<size_t>(1, std::min(resident, (size_t)(n + 255) / 256));
+  const size_t lanes = blocks * 256;
   const size_t cap = max_len ? max_len : 1;
   const size_t o_scr = (sizeof(Status) + 255) / 256 * 256;  // lists after the status
   if ((rc = S->ws.ensure(o_scr + lanes * 2 * cap * smem_list_entry_bytes()))) return rc;
@@ -216,7 +220,7 @@ int bsw_fm_smem_device(bsw_ctx* c, const bsw_fm_entry* E, const bsw_fm_meta* met
   if (reads) launch_codes(reads, read_off, n, st, 0, s);
   HIPCHK(hipEventRecord(S->ev[0], s));
   launch_fm_smem(E, *meta, reads, read_off, n, (uint32_t)cap, (char*)S->ws.p + o_scr,
-                 SMEM_BLOCKS, st, out, counts, s);
+                 (unsigned)blocks, st, out, counts, s);
   HIPCHK(hipEventRecord(S->ev[1], s));
   HIPCHK(hipMemcpyAsync(S->h_st, st, sizeof(Status), hipMemcpyDeviceToHost, s));
   HIPCHK(hipGetLastError());

@@ -52,11 +52,16 @@ __device__ __forceinline__ void back_ext(const bsw_fm_entry* __restrict__ E,
   uint32_t lo[4], hi[4];
   occ4(E, (int64_t)k - 1, lo);
   occ4(E, (int64_t)(k + s) - 1, hi);
+  // constant indices only (a runtime index would put the arrays in memory)
+  const uint32_t s0 = hi[0] - lo[0], s1 = hi[1] - lo[1], s2_ = hi[2] - lo[2],
+                 s3 = hi[3] - lo[3];
   uint64_t nl = l + (k <= meta.primary && meta.primary < k + s ? 1 : 0);
-  for (int d = 3; d > (int)c; --d) nl += hi[d] - lo[d];
-  k2 = meta.C[c] + lo[c];
+  nl += (c < 3 ? s3 : 0u) + (c < 2 ? s2_ : 0u) + (c < 1 ? s1 : 0u);
+  const uint32_t loc = c == 0 ? lo[0] : c == 1 ? lo[1] : c == 2 ? lo[2] : lo[3];
+  const uint64_t Cc = c == 0 ? meta.C[0] : c == 1 ? meta.C[1] : c == 2 ? meta.C[2] : meta.C[3];
+  k2 = Cc + loc;
   l2 = nl;
-  s2 = hi[c] - lo[c];
+  s2 = c == 0 ? s0 : c == 1 ? s1 : c == 2 ? s2_ : s3;
 }
 
 // Forward extension (Algorithm 3): Xc from X, by extending revcomp(X) on

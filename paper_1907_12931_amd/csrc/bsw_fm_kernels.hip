@@ -115,8 +115,10 @@ k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
         continue;
       }
       // forward (Algorithm 3) from the single base at x
-      uint64_t k = meta.C[c], l = meta.C[3 - c];
-      uint64_t s = (c < 3 ? meta.C[c + 1] : meta.rows) - meta.C[c];
+      const uint64_t C0 = meta.C[0], C1 = meta.C[1], C2 = meta.C[2], C3 = meta.C[3];
+      uint64_t k = c == 0 ? C0 : c == 1 ? C1 : c == 2 ? C2 : C3;
+      uint64_t l = c == 0 ? C3 : c == 1 ? C2 : c == 2 ? C1 : C0;
+      uint64_t s = (c == 0 ? C1 : c == 1 ? C2 : c == 2 ? C3 : meta.rows) - k;
       uint32_t end = (uint32_t)x + 1;
       ListEnt* cur = bufA;
       int ncur = 0;
@@ -196,6 +198,15 @@ void launch_smem_check(const uint64_t* off, int64_t n, uint32_t cap, Status* st,
 }
 
 size_t smem_list_entry_bytes() { return sizeof(ListEnt); }
+
+int fm_smem_blocks_per_cu() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fm_smem, 256, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    b = 1;
+  }
+  return b < 1 ? 1 : b;
+}
 
 void launch_fm_smem(const bsw_fm_entry* E, const bsw_fm_meta& meta, const uint8_t* reads,
                     const uint64_t* off, int64_t n, uint32_t cap, void* scratch,

@@ -802,6 +802,8 @@ void ctx_set_cells(bsw_ctx* c, unsigned long long cells) { c->last_cells = cells
 
 int ctx_set_device(bsw_ctx* c) { return set_device(c); }
 
+int ctx_num_cu(const bsw_ctx* c) { return c->num_cu; }
+
 void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*)) {
   c->pending = true;
   c->pending_stream = s;

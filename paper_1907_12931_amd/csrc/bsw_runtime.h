@@ -111,6 +111,7 @@ double* ctx_timing(bsw_ctx* c);
 void ctx_add_cells(bsw_ctx* c, unsigned long long cells);
 void ctx_set_cells(bsw_ctx* c, unsigned long long cells);
 int ctx_set_device(bsw_ctx* c);
+int ctx_num_cu(const bsw_ctx* c);
 // Mark the context as having an asynchronous call in flight on s whose
 // completion is checked by done (bsw_ctx_wait calls it).
 void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*));
