@@ -61,7 +61,7 @@ def traffic_from_profile(kernel, work, profile="bsw"):
             continue
         text = open(os.path.join(prof_dir, name)).read()
         fields = dict(re.findall(r"^- (\w+): `([^`]*)`", text, flags=re.M))
-        if (fields.get("kernel") == kernel and fields.get("source_sha256") == digest
+        if (fields.get("kernel") == kernel.split(" (")[0] and fields.get("source_sha256") == digest
                 and fields.get(work_field) == str(work)
                 and "traffic_bytes_per_launch" in fields):
             return int(fields["traffic_bytes_per_launch"])
