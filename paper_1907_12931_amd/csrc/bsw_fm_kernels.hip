@@ -10,8 +10,8 @@
 //   k_smem_check per read: offsets ordered, length within the list capacity
 //   k_fm_smem    the SMEMs of every read (Algorithms 3 and 4 around each
 //                pivot, the pivot moving to the end of the longest forward
-//                match), one read per lane, the interval lists of a lane in
-//                its own slot of scratch memory
+//                match), one read per lane, the interval lists of the lanes
+//                interleaved in scratch memory
 #include <hip/hip_runtime.h>
 
 #include "../../include/bsw.h"
@@ -98,8 +98,9 @@ k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
   if (st->bad) return;
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t G = (int64_t)gridDim.x * blockDim.x;
-  ListEnt* bufA = scratch + (size_t)g * 2 * cap;
-  ListEnt* bufB = bufA + cap;
+  // entry j of list b of this lane: the lanes' entries sit side by side, so
+  // the lanes of a wave that touch their entry j at once share lines
+#define LIST(b, j) scratch[((size_t)(b) * cap + (size_t)(j)) * (size_t)G + (size_t)g]
   const uint64_t base = off[0];
   unsigned long long steps = 0;  // this lane's extension steps
   for (int64_t r = g; r < n; r += G) {
@@ -120,38 +121,38 @@ k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
       uint64_t l = c == 0 ? C3 : c == 1 ? C2 : c == 2 ? C1 : C0;
       uint64_t s = (c == 0 ? C1 : c == 1 ? C2 : c == 2 ? C3 : meta.rows) - k;
       uint32_t end = (uint32_t)x + 1;
-      ListEnt* cur = bufA;
+      int cur = 0;  // list ids: 0 and 1
       int ncur = 0;
       int i = x + 1;
       for (; i < L; ++i) {
         c = X[i];
         if (c > 3) {
-          cur[ncur++] = {k, l, (uint32_t)s, end};
+          LIST(cur, ncur++) = {k, l, (uint32_t)s, end};
           break;
         }
         uint64_t k2, l2, s2;
         fwd_ext(E, meta, k, l, s, c, k2, l2, s2);
         ++steps;
-        if (s2 != s) cur[ncur++] = {k, l, (uint32_t)s, end};
+        if (s2 != s) LIST(cur, ncur++) = {k, l, (uint32_t)s, end};
         if (s2 == 0) break;
         k = k2;
         l = l2;
         s = s2;
         end = (uint32_t)i + 1;
       }
-      if (i == L) cur[ncur++] = {k, l, (uint32_t)s, end};
-      const int next = (int)cur[ncur - 1].end;
+      if (i == L) LIST(cur, ncur++) = {k, l, (uint32_t)s, end};
+      const int next = (int)LIST(cur, ncur - 1).end;
       // backward (Algorithm 4), longest forward match first
-      ListEnt* prev = bufB;
+      int prev = 1;
       int nprev = ncur;
-      for (int j = 0; j < ncur; ++j) prev[j] = cur[ncur - 1 - j];
-      cur = bufA;
+      for (int j = 0; j < ncur; ++j) LIST(prev, j) = LIST(0, ncur - 1 - j);
+      cur = 0;
       const int first = cnt;
       for (int ii = x - 1;; --ii) {
         const int cc = ii >= 0 && X[ii] < 4 ? (int)X[ii] : -1;
         ncur = 0;
         for (int j = 0; j < nprev; ++j) {
-          const ListEnt p = prev[j];
+          const ListEnt p = LIST(prev, j);
           uint64_t k2 = 0, l2 = 0, s2 = 0;
           if (cc >= 0) {
             back_ext(E, meta, p.k, p.l, p.s, (uint32_t)cc, k2, l2, s2);
@@ -160,12 +161,12 @@ k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
           if (cc < 0 || s2 == 0) {
             if (ncur == 0 && (cnt == first || ii + 1 < (int)o[cnt - 1].start) && cnt < L)
               o[cnt++] = {(uint32_t)(ii + 1), p.end, p.k, p.l, (uint64_t)p.s};
-          } else if (ncur == 0 || (uint32_t)s2 != cur[ncur - 1].s) {
-            cur[ncur++] = {k2, l2, (uint32_t)s2, p.end};
+          } else if (ncur == 0 || (uint32_t)s2 != LIST(cur, ncur - 1).s) {
+            LIST(cur, ncur++) = {k2, l2, (uint32_t)s2, p.end};
           }
         }
         if (ncur == 0) break;
-        ListEnt* t = prev;
+        const int t = prev;
         prev = cur;
         cur = t;
         nprev = ncur;
@@ -187,6 +188,7 @@ k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
     steps += ((unsigned long long)hi << 32) | lo;
   }
   if ((threadIdx.x & 63) == 0) atomicAdd(&st->cls_cells[0], steps);
+#undef LIST
 }
 
 void launch_smem_check(const uint64_t* off, int64_t n, uint32_t cap, Status* st,
