@@ -73,4 +73,45 @@ __device__ __forceinline__ void fwd_ext(const bsw_fm_entry* __restrict__ E,
   back_ext(E, meta, l, k, s, 3 - c, l2, k2, s2);
 }
 
+// The same steps with 32-bit rows (an index built by bsw_fm_build has fewer
+// than 2^32 rows, so k + s never wraps): fewer registers per lane.  tp1 is
+// t + 1 (0 for t = -1).
+__device__ __forceinline__ void occ4_32(const bsw_fm_entry* __restrict__ E, uint32_t tp1,
+                                        uint32_t o[4]) {
+  if (tp1 == 0) {
+    o[0] = o[1] = o[2] = o[3] = 0;
+    return;
+  }
+  occ4(E, (int64_t)(tp1 - 1), o);
+}
+
+struct FmRows32 {
+  uint32_t C0, C1, C2, C3, primary, rows;
+};
+
+__device__ __forceinline__ void back_ext32(const bsw_fm_entry* __restrict__ E,
+                                           const FmRows32& m, uint32_t k, uint32_t l,
+                                           uint32_t s, uint32_t c, uint32_t& k2, uint32_t& l2,
+                                           uint32_t& s2) {
+  uint32_t lo[4], hi[4];
+  occ4_32(E, k, lo);
+  occ4_32(E, k + s, hi);
+  const uint32_t s0 = hi[0] - lo[0], s1 = hi[1] - lo[1], s2_ = hi[2] - lo[2],
+                 s3 = hi[3] - lo[3];
+  uint32_t nl = l + (k <= m.primary && m.primary < k + s ? 1u : 0u);
+  nl += (c < 3 ? s3 : 0u) + (c < 2 ? s2_ : 0u) + (c < 1 ? s1 : 0u);
+  const uint32_t loc = c == 0 ? lo[0] : c == 1 ? lo[1] : c == 2 ? lo[2] : lo[3];
+  const uint32_t Cc = c == 0 ? m.C0 : c == 1 ? m.C1 : c == 2 ? m.C2 : m.C3;
+  k2 = Cc + loc;
+  l2 = nl;
+  s2 = c == 0 ? s0 : c == 1 ? s1 : c == 2 ? s2_ : s3;
+}
+
+__device__ __forceinline__ void fwd_ext32(const bsw_fm_entry* __restrict__ E,
+                                          const FmRows32& m, uint32_t k, uint32_t l,
+                                          uint32_t s, uint32_t c, uint32_t& k2, uint32_t& l2,
+                                          uint32_t& s2) {
+  back_ext32(E, m, l, k, s, 3 - c, l2, k2, s2);
+}
+
 }  // namespace bsw

@@ -73,9 +73,8 @@ k_smem_check(const uint64_t* __restrict__ off, int64_t n, uint32_t cap, Status* 
 }
 
 namespace {
-struct ListEnt {  // a bi-interval and the read end of its match
-  uint64_t k, l;
-  uint32_t s, end;
+struct ListEnt {  // a bi-interval (32-bit rows) and the read end of its match
+  uint32_t k, l, s, end;
 };
 }  // namespace
 
@@ -102,6 +101,8 @@ k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
   // the lanes of a wave that touch their entry j at once share lines
 #define LIST(b, j) scratch[((size_t)(b) * cap + (size_t)(j)) * (size_t)G + (size_t)g]
   const uint64_t base = off[0];
+  const FmRows32 m32 = {(uint32_t)meta.C[0], (uint32_t)meta.C[1], (uint32_t)meta.C[2],
+                        (uint32_t)meta.C[3], (uint32_t)meta.primary, (uint32_t)meta.rows};
   unsigned long long steps = 0;  // this lane's extension steps
   for (int64_t r = g; r < n; r += G) {
     const uint8_t* X = reads + off[r];
@@ -116,10 +117,9 @@ k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
         continue;
       }
       // forward (Algorithm 3) from the single base at x
-      const uint64_t C0 = meta.C[0], C1 = meta.C[1], C2 = meta.C[2], C3 = meta.C[3];
-      uint64_t k = c == 0 ? C0 : c == 1 ? C1 : c == 2 ? C2 : C3;
-      uint64_t l = c == 0 ? C3 : c == 1 ? C2 : c == 2 ? C1 : C0;
-      uint64_t s = (c == 0 ? C1 : c == 1 ? C2 : c == 2 ? C3 : meta.rows) - k;
+      uint32_t k = c == 0 ? m32.C0 : c == 1 ? m32.C1 : c == 2 ? m32.C2 : m32.C3;
+      uint32_t l = c == 0 ? m32.C3 : c == 1 ? m32.C2 : c == 2 ? m32.C1 : m32.C0;
+      uint32_t s = (c == 0 ? m32.C1 : c == 1 ? m32.C2 : c == 2 ? m32.C3 : m32.rows) - k;
       uint32_t end = (uint32_t)x + 1;
       int cur = 0;  // list ids: 0 and 1
       int ncur = 0;
@@ -127,20 +127,20 @@ k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
       for (; i < L; ++i) {
         c = X[i];
         if (c > 3) {
-          LIST(cur, ncur++) = {k, l, (uint32_t)s, end};
+          LIST(cur, ncur++) = {k, l, s, end};
           break;
         }
-        uint64_t k2, l2, s2;
-        fwd_ext(E, meta, k, l, s, c, k2, l2, s2);
+        uint32_t k2, l2, s2;
+        fwd_ext32(E, m32, k, l, s, c, k2, l2, s2);
         ++steps;
-        if (s2 != s) LIST(cur, ncur++) = {k, l, (uint32_t)s, end};
+        if (s2 != s) LIST(cur, ncur++) = {k, l, s, end};
         if (s2 == 0) break;
         k = k2;
         l = l2;
         s = s2;
         end = (uint32_t)i + 1;
       }
-      if (i == L) LIST(cur, ncur++) = {k, l, (uint32_t)s, end};
+      if (i == L) LIST(cur, ncur++) = {k, l, s, end};
       const int next = (int)LIST(cur, ncur - 1).end;
       // backward (Algorithm 4), longest forward match first
       int prev = 1;
@@ -153,16 +153,16 @@ k_fm_smem(const bsw_fm_entry* __restrict__ E, bsw_fm_meta meta,
         ncur = 0;
         for (int j = 0; j < nprev; ++j) {
           const ListEnt p = LIST(prev, j);
-          uint64_t k2 = 0, l2 = 0, s2 = 0;
+          uint32_t k2 = 0, l2 = 0, s2 = 0;
           if (cc >= 0) {
-            back_ext(E, meta, p.k, p.l, p.s, (uint32_t)cc, k2, l2, s2);
+            back_ext32(E, m32, p.k, p.l, p.s, (uint32_t)cc, k2, l2, s2);
             ++steps;
           }
           if (cc < 0 || s2 == 0) {
             if (ncur == 0 && (cnt == first || ii + 1 < (int)o[cnt - 1].start) && cnt < L)
-              o[cnt++] = {(uint32_t)(ii + 1), p.end, p.k, p.l, (uint64_t)p.s};
-          } else if (ncur == 0 || (uint32_t)s2 != LIST(cur, ncur - 1).s) {
-            LIST(cur, ncur++) = {k2, l2, (uint32_t)s2, p.end};
+              o[cnt++] = {(uint32_t)(ii + 1), p.end, (uint64_t)p.k, (uint64_t)p.l, (uint64_t)p.s};
+          } else if (ncur == 0 || s2 != LIST(cur, ncur - 1).s) {
+            LIST(cur, ncur++) = {k2, l2, s2, p.end};
           }
         }
         if (ncur == 0) break;
