@@ -48,11 +48,14 @@ def traffic_from_profile(kernel, work, profile="bsw"):
     suffix-array lookup); else None."""
     import hashlib
     import re
-    src_name, work_field = {"bsw": ("bsw_kernels.hip", "cells_per_launch"),
-                            "sal": ("bsw_sal_kernels.hip", "alg_bytes_per_launch"),
-                            "fm": ("bsw_fm_kernels.hip", "alg_bytes_per_launch")}[profile]
-    src = os.path.join(ROOT, "paper_1907_12931_amd", "csrc", src_name)
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    srcs, work_field = {"bsw": (["bsw_kernels.hip"], "cells_per_launch"),
+                        "sal": (["bsw_sal_kernels.hip"], "alg_bytes_per_launch"),
+                        "fm": (["bsw_fm_kernels.hip", "bsw_fm_device.h"],
+                               "alg_bytes_per_launch")}[profile]
+    h = hashlib.sha256()
+    for name in srcs:  # the kernel source and the device code it includes
+        h.update(open(os.path.join(ROOT, "paper_1907_12931_amd", "csrc", name), "rb").read())
+    digest = h.hexdigest()
     prof_dir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(prof_dir):
         return None
