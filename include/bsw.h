@@ -185,8 +185,9 @@ int bsw_ctx_wait(bsw_ctx* ctx);
 int bsw_ctx_last_timing(bsw_ctx* ctx, double out4[4]);
 
 /* Band cells settled by the last completed call (all of its BSW passes;
- * the rerun of pairs that overflowed a narrow record width counts again).
- * Returns BSW_OK. */
+ * the rerun of pairs that overflowed a narrow record width counts again);
+ * after bsw_fm_smem_device the extension steps it ran, after the other
+ * index calls 0.  Returns BSW_OK. */
 int bsw_ctx_last_cells(bsw_ctx* ctx, int64_t* cells);
 
 /* Per-launch record of the last completed call's DP kernels: for launch k,
