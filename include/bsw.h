@@ -29,6 +29,10 @@
  *    recent one of the calling thread.  On an error no output is written.
  *  - n = 0 is a no-op that returns BSW_OK.
  *  - One context per host thread (a context is not thread-safe).
+ *  - A context holds at most one asynchronous call: until bsw_ctx_wait has
+ *    returned for it, every call that enqueues work on the context returns
+ *    BSW_EBUSY and enqueues nothing (the pending call's queued work still
+ *    reads the context's scoring table, status block and captured graph).
  */
 #ifndef BSW_H
 #define BSW_H
@@ -85,7 +89,8 @@ enum {
   BSW_ENOMEM = -2,  /* device or host allocation failed                    */
   BSW_EDEVICE = -3, /* no usable gfx950 device, or a HIP call failed       */
   BSW_ETOOBIG = -4, /* request larger than the context's HBM budget        */
-  BSW_EBUSY = -5,   /* serving: no free slot within the timeout            */
+  BSW_EBUSY = -5,   /* serving: queue full; context: an asynchronous call
+                     * is still pending (call bsw_ctx_wait)                 */
   BSW_ETIMEOUT = -6 /* serving: ticket not complete within the timeout     */
 };
 
@@ -103,7 +108,11 @@ typedef struct bsw_ctx_opts {
   int32_t device;          /* HIP device ordinal                           */
   int32_t min_lane_bits;   /* 0 = pick 8/16/32 from each pair's score bound;
                             * 16 or 32 forces at least that width           */
-  int32_t reserved;        /* must be 0                                     */
+  int32_t max_groups;      /* batched path: cap on the persistent workgroups
+                            * of each kernel class (0 = as many as are
+                            * resident on the device); a cap below a class's
+                            * tile count makes every workgroup take several
+                            * tiles from the class queue                    */
   int32_t path;            /* BSW_PATH_BATCHED or BSW_PATH_PLAIN            */
   size_t  hbm_budget;      /* cap on the context's device arena in bytes
                             * (0 = none); a call that would need more fails
@@ -199,6 +208,17 @@ int bsw_ctx_last_cells(bsw_ctx* ctx, int64_t* cells);
  * Returns the number of launches (may exceed max). */
 int bsw_ctx_last_kernels(bsw_ctx* ctx, int32_t* cls, int64_t* cells, double* ms,
                          int32_t max);
+
+/* Work behind the cells of the last completed call's DP launches, in the
+ * order of bsw_ctx_last_kernels: work[k] = lane-cells launch k stepped
+ * through (each wave's column span of every row it ran, times its 64
+ * lanes, lanes that were padding or had already stopped included), so
+ * that cells[k] / work[k] is the share of the launch's work that the
+ * method needed (Sec. 6, the useful-cell share of the inter-task kernel).
+ * 0 for kernels that do not count it (one pair per wave or per lane with
+ * a private buffer).  At most max entries are written.  Returns the number
+ * of launches. */
+int bsw_ctx_last_work(bsw_ctx* ctx, int64_t* work, int32_t max);
 
 /* Name of a kernel class ("lane8_q256" = one pair per lane, 8-bit row
  * buffer, queries up to 256; "rerun" = one pair per wave with 32-bit values,
@@ -491,6 +511,25 @@ int bsw_fm_smem_device(bsw_ctx* ctx, const bsw_fm_entry* entries, const bsw_fm_m
                        const uint8_t* reads, const uint64_t* read_off, int64_t n_reads,
                        uint32_t max_len, bsw_smem* out, int32_t* counts, void* stream,
                        int32_t async);
+
+/* Measured integer-VALU peak of a device: the rate that the extension
+ * kernels' operation counts are compared with (they are integer max-plus
+ * dynamic programming, so the vector ALU bounds them; Sec. 5.4.1 picks 8-
+ * or 16-bit lanes to put more cells through it).  Every lane of a grid of
+ * 8 waves per SIMD over every CU runs eight independent chains of one
+ * instruction kind; *instr_per_s receives lane-instructions per second
+ * (best of three timed runs after a warm-up), *ops_per_s (nullable) the
+ * operations per second, two per lane-instruction for the packed 16-bit
+ * kinds.  Blocking; allocates a small scratch buffer on the device.
+ * Returns BSW_EINVAL for an unknown kind, BSW_EDEVICE if the device is
+ * missing or a HIP call fails. */
+enum {
+  BSW_PEAK_ADD_U32 = 0,    /* v_add_u32                                    */
+  BSW_PEAK_MAX3_I32 = 1,   /* v_max3_i32                                   */
+  BSW_PEAK_PK_ADD_U16 = 2, /* v_pk_add_u16 (two 16-bit additions)          */
+  BSW_PEAK_PK_MAX_I16 = 3  /* v_pk_max_i16 (two 16-bit maxima)             */
+};
+int bsw_valu_peak(int32_t device, int32_t kind, double* instr_per_s, double* ops_per_s);
 
 /* Text of the calling thread's most recent error ("" if none). */
 const char* bsw_last_error(void);

@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
 
 class CtxOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("min_lane_bits", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("max_groups", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("hbm_budget", ctypes.c_size_t), ("tune_cache", ctypes.c_char_p),
                 ("no_graph", ctypes.c_int32)]
 
@@ -172,10 +172,27 @@ def lib():
         L.bsw_server_wait.argtypes = [_VP, ctypes.c_uint64, ctypes.c_int32]
         L.bsw_server_stats.restype = ctypes.c_int
         L.bsw_server_stats.argtypes = [_VP, ctypes.POINTER(ServerReport), ctypes.c_int32]
+        L.bsw_ctx_last_work.restype = ctypes.c_int
+        L.bsw_ctx_last_work.argtypes = [_VP, _VP, ctypes.c_int32]
+        L.bsw_valu_peak.restype = ctypes.c_int
+        L.bsw_valu_peak.argtypes = [ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
         if L.bsw_abi_version() != 1:
             raise BswError(EDEVICE, "libbsw.so ABI version mismatch")
         _lib = L
     return _lib
+
+
+PEAK_KINDS = {"v_add_u32": 0, "v_max3_i32": 1, "v_pk_add_u16": 2, "v_pk_max_i16": 3}
+
+
+def valu_peak(kind, device=0):
+    """Measured integer-VALU rate (``bsw_valu_peak``): returns
+    (lane-instructions/s, operations/s) for one instruction kind."""
+    ip, op = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().bsw_valu_peak(device, PEAK_KINDS[kind], ctypes.byref(ip), ctypes.byref(op)))
+    return ip.value, op.value
 
 
 def last_error() -> str:
@@ -206,10 +223,11 @@ class Context:
     """A library context on one device (see ``bsw_ctx_create``)."""
 
     def __init__(self, device=0, min_lane_bits=0, path=PATH_BATCHED,
-                 hbm_budget=0, tune_cache=None, graph=True):
+                 hbm_budget=0, tune_cache=None, graph=True, max_groups=0):
         # the library copies the path; the bytes only need to live for the call
         tc = tune_cache.encode() if tune_cache else None
-        o = CtxOpts(device, min_lane_bits, 0, path, hbm_budget, tc, 0 if graph else 1)
+        o = CtxOpts(device, min_lane_bits, max_groups, path, hbm_budget, tc,
+                    0 if graph else 1)
         h = _VP()
         _check(lib().bsw_ctx_create(ctypes.byref(h), ctypes.byref(o)))
         self._h = h
@@ -389,6 +407,15 @@ class Context:
             _check(n)
         return [(lib().bsw_class_name(int(cls[k])).decode(), int(cells[k]), float(ms[k]))
                 for k in range(min(n, 32))]
+
+    def last_work(self):
+        """Per DP launch of the last call (order of ``last_kernels``): the
+        lane-cells it stepped through (``bsw_ctx_last_work``)."""
+        work = np.zeros(32, dtype=np.int64)
+        n = lib().bsw_ctx_last_work(self._h, work.ctypes.data, 32)
+        if n < 0:
+            _check(n)
+        return [int(x) for x in work[:min(n, 32)]]
 
     def last_timing(self):
         """(pipeline_ms, prep_bin_ms, dp_ms, dp_launches) of the last call."""

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsw.so")
 SOURCES = ["bsw_kernels.hip", "bsw_seed_kernels.hip", "bsw_sal_kernels.hip", "bsw_host.cpp",
            "bsw_fm_kernels.hip", "bsw_server.cpp", "bsw_seeds.cpp", "bsw_sal.cpp",
-           "bsw_fm.cpp"]
+           "bsw_fm.cpp", "bsw_peak.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -26,17 +26,24 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *lang,
-               "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append(["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *lang,
+                     "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # the sources compile independently; the largest one sets the time
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        list(ex.map(compile_one, cmds))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -159,6 +159,7 @@ int bsw_fm_backward_search_device(bsw_ctx* c, const bsw_fm_entry* E, const bsw_f
                                   const uint8_t* pat, const uint64_t* pat_off, int64_t n,
                                   bsw_bi_interval* out, void* stream, int32_t async) {
   if (!c) return set_error(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
   if (n < 0 || n > 0x7fffffffLL)
     return set_error(BSW_EINVAL, "n = %lld out of range", (long long)n);
   if (n == 0) return BSW_OK;
@@ -194,6 +195,7 @@ int bsw_fm_smem_device(bsw_ctx* c, const bsw_fm_entry* E, const bsw_fm_meta* met
                        uint32_t max_len, bsw_smem* out, int32_t* counts, void* stream,
                        int32_t async) {
   if (!c) return set_error(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
   if (n < 0 || n > 0x7fffffffLL)
     return set_error(BSW_EINVAL, "n_reads = %lld out of range", (long long)n);
   if (n == 0) return BSW_OK;

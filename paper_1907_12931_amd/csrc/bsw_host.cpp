@@ -46,7 +46,8 @@ void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
                  const KParams* kp, bsw_result* out, bsw_diag* diag,
                  uint32_t* tile_ctr, const Status* st, uint32_t* qtiles,
                  PairDesc* ovf, long long* ovf_count, int ring, bool sym,
-                 unsigned long long* cls_cells, hipStream_t s);
+                 unsigned long long* cls_cells, unsigned long long* work_cells,
+                 hipStream_t s);
 void launch_wave(unsigned blocks, const PairDesc* desc, const long long* range,
                  const uint8_t* q, const uint8_t* t, const KParams* kp, bsw_result* out,
                  bsw_diag* diag, uint32_t* ctr, const Status* st,
@@ -204,6 +205,7 @@ struct bsw_ctx {
   int n_launch = 0;
   double lms[MAXL] = {};
   unsigned long long lcells[MAXL] = {};
+  unsigned long long lwork[MAXL] = {};
   Budget budget;
   DevBuf ws;       // workspace
   DevBuf in;       // staged host inputs
@@ -230,6 +232,7 @@ struct bsw_ctx {
   unsigned long long last_cells = 0;  // band cells of the last finished call
   // captured batched pipeline and what it was captured for
   hipGraphExec_t gexec = nullptr;
+  hipStream_t gexec_stream = nullptr;  // stream of the graph's last launch
   GraphKey gkey;
   int n_graph_launch = 0;
   // launch shapes of the batched path (defaults, a cache entry or
@@ -350,17 +353,22 @@ BatchedPlan plan_batched(bsw_ctx* c, int wmax, bool sym) {
   BatchedPlan p;
   for (int cls = 0; cls < CLS_LONG; ++cls) {
     int per_cu = c->blocks_per_cu[1][cls];
-    if (cls < CLS_W32) {
+    if (cls < CLS_W16) {
+      // register-row kernels: occupancy set by registers and the mirror
+      per_cu = c->blocks_per_cu[sym ? 1 : 0][cls];
+    } else if (cls < CLS_W32) {
       p.ring[cls] = lane8_ring_chunks(cls, wmax);
       per_cu = chunked_per_cu(c, cls, sym, p.ring[cls]);
     }
     p.blocks[cls] = (int64_t)tuned_per_cu(c, cls, per_cu) * c->num_cu;
-    if (cls < CLS_W32) {
+    if (c->opts.max_groups > 0) p.blocks[cls] = std::min<int64_t>(p.blocks[cls], c->opts.max_groups);
+    if (cls >= CLS_W16 && cls < CLS_W32) {
       p.qt_off[cls] = p.qt_words;
       p.qt_words += (size_t)p.blocks[cls] * lane8_qtile_words(cls);
     }
   }
   p.blocks[NCLS] = (int64_t)c->wave_per_cu * c->num_cu;
+  if (c->opts.max_groups > 0) p.blocks[NCLS] = std::min<int64_t>(p.blocks[NCLS], c->opts.max_groups);
   return p;
 }
 
@@ -397,7 +405,7 @@ int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan&
     launch_lane(cls, true, (unsigned)p.blocks[cls], w.desc, w.cls_range + 2 * cls, a.q,
                 a.t, c->d_kp, a.out, a.diag, w.ctr + cls, st,
                 cls < CLS_W32 ? qt + p.qt_off[cls] : nullptr, w.ovf, &st->ovf_range[1],
-                p.ring[cls], sym, &st->cls_cells[cls], ls);
+                p.ring[cls], sym, &st->cls_cells[cls], &st->work_cells[cls], ls);
     if ((rc = end_launch(c, ls))) return rc;
   }
   for (int k = 0; k < nside; ++k) {
@@ -529,7 +537,12 @@ int run_batched(bsw_ctx* c, const Args& a, hipStream_t s) {
   key.sym = sym;
   key.tune = c->tunes[c->kind];
   if (!c->gexec || !same_key(key, c->gkey)) {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    // an executable graph is destroyed only once its last launch has
+    // finished: the runtime may still be walking it otherwise
+    if (c->gexec) {
+      HIPCHK(hipStreamSynchronize(c->gexec_stream));
+      (void)hipGraphExecDestroy(c->gexec);
+    }
     c->gexec = nullptr;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     rc = enqueue_batched(c, a, w, p, sym, s);
@@ -552,6 +565,7 @@ int run_batched(bsw_ctx* c, const Args& a, hipStream_t s) {
   }
   c->n_launch = c->n_graph_launch;
   HIPCHK(hipEventRecord(c->ev[0], s));
+  c->gexec_stream = s;
   HIPCHK(hipGraphLaunch(c->gexec, s));
   HIPCHK(hipEventRecord(c->ev[3], s));
   return BSW_OK;
@@ -637,9 +651,9 @@ int run_plain(bsw_ctx* c, const Args& a, hipStream_t s) {
     if (count <= 0) continue;
     const int wpb = lane_waves_per_block(cls);
     blocks[cls] = ((count + 63) / 64 + wpb - 1) / wpb;
-    if (cls < CLS_W32) {
+    if (cls < CLS_W32) (cls < CLS_W16 ? any8 : any16) = true;
+    if (cls >= CLS_W16 && cls < CLS_W32) {
       ring[cls] = lane8_ring_chunks(cls, wmax);
-      (cls < CLS_W16 ? any8 : any16) = true;
       qt_off[cls] = qt_words;
       qt_words += (size_t)blocks[cls] * lane8_qtile_words(cls);
     }
@@ -657,7 +671,8 @@ int run_plain(bsw_ctx* c, const Args& a, hipStream_t s) {
     if ((rc = begin_launch(c, cls, s))) return rc;
     launch_lane(cls, false, (unsigned)blocks[cls], w.desc, w.cls_range + 2 * cls, a.q, a.t,
                 c->d_kp, a.out, a.diag, w.ctr + cls, st, qt ? qt + qt_off[cls] : nullptr,
-                w.ovf, &st->ovf_range[1], ring[cls], sym, &st->cls_cells[cls], s);
+                w.ovf, &st->ovf_range[1], ring[cls], sym, &st->cls_cells[cls],
+                &st->work_cells[cls], s);
     if ((rc = end_launch(c, s))) return rc;
   }
   if (c->h_cls[2 * CLS_LONG + 1] > 0) {
@@ -720,6 +735,7 @@ void record_timing(bsw_ctx* c) {
   for (int k = 0; k < c->n_launch; ++k) {
     c->lms[k] = c->graph_call ? 0.0 : elapsed(c->lev0[k], c->lev[k]);
     c->lcells[k] = c->h_status->cls_cells[c->lcls[k]];
+    c->lwork[k] = c->h_status->work_cells[c->lcls[k]];
   }
 }
 
@@ -804,6 +820,14 @@ int ctx_set_device(bsw_ctx* c) { return set_device(c); }
 
 int ctx_num_cu(const bsw_ctx* c) { return c->num_cu; }
 
+int ctx_check_idle(const bsw_ctx* c) {
+  if (c->pending)
+    return fail(BSW_EBUSY,
+                "an asynchronous call is still pending on this context: call "
+                "bsw_ctx_wait first");
+  return BSW_OK;
+}
+
 void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*)) {
   c->pending = true;
   c->pending_stream = s;
@@ -864,6 +888,7 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
   if (o.min_lane_bits != 0 && o.min_lane_bits != 8 && o.min_lane_bits != 16 &&
       o.min_lane_bits != 32)
     return fail(BSW_EINVAL, "min_lane_bits must be 0, 8, 16 or 32");
+  if (o.max_groups < 0) return fail(BSW_EINVAL, "max_groups must be >= 0");
   if (o.path != BSW_PATH_BATCHED && o.path != BSW_PATH_PLAIN)
     return fail(BSW_EINVAL, "unknown path %d", o.path);
   bsw_ctx* c = new (std::nothrow) bsw_ctx;
@@ -931,7 +956,10 @@ void bsw_ctx_destroy(bsw_ctx* c) {
   c->res.release();
   c->longbuf.release();
   c->qtiles.release();
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->gexec) {
+    (void)hipStreamSynchronize(c->gexec_stream);
+    (void)hipGraphExecDestroy(c->gexec);
+  }
   if (c->h_kp) (void)hipHostFree(c->h_kp);
   if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->h_cls) (void)hipHostFree(c->h_cls);
@@ -958,6 +986,7 @@ int bsw_extend_batch_device(bsw_ctx* c, int64_t n, const uint8_t* q,
                             int32_t n_params, bsw_result* out, bsw_diag* diag,
                             void* stream, int32_t async) {
   if (!c) return fail(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
   if (n < 0 || n > 0x7fffffffLL) return fail(BSW_EINVAL, "n = %lld out of range", (long long)n);
   if (n == 0) return BSW_OK;
   int rc = check_params(params, n_params);
@@ -984,6 +1013,7 @@ int bsw_ctx_tune(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_off,
                  const uint8_t* param_id, const bsw_params* params, int32_t n_params,
                  bsw_result* out, int32_t reps, double* best_ms) {
   if (!c) return fail(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
   if (c->opts.path != BSW_PATH_BATCHED)
     return fail(BSW_EINVAL, "tuning applies to the batched path");
   if (n < 1 || n > 0x7fffffffLL) return fail(BSW_EINVAL, "n = %lld out of range", (long long)n);
@@ -1039,6 +1069,13 @@ int bsw_ctx_last_kernels(bsw_ctx* c, int32_t* cls, int64_t* cells, double* ms,
   return c->n_launch;
 }
 
+int bsw_ctx_last_work(bsw_ctx* c, int64_t* work, int32_t max) {
+  if (!c) return fail(BSW_EINVAL, "ctx is NULL");
+  const int n = std::min((int)max, c->n_launch);
+  for (int k = 0; k < n && work; ++k) work[k] = (int64_t)c->lwork[k];
+  return c->n_launch;
+}
+
 const char* bsw_class_name(int32_t cls) {
   static const char* names[NCLS + 1] = {
       "lane8_q32",  "lane8_q64",  "lane8_q96",  "lane8_q128", "lane8_q160",
@@ -1065,6 +1102,7 @@ int bsw_extend_batch(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_
                      const uint8_t* param_id, const bsw_params* params,
                      int32_t n_params, bsw_result* out, bsw_diag* diag) {
   if (!c) return fail(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
   if (n < 0 || n > 0x7fffffffLL) return fail(BSW_EINVAL, "n = %lld out of range", (long long)n);
   if (n == 0) return BSW_OK;
   int rc = check_params(params, n_params);

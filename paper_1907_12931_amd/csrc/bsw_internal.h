@@ -64,6 +64,10 @@ struct Status {
   unsigned long long long_max;   // largest query length in the long class
   long long ovf_range[2];        // {0, number of pairs queued for the rerun}
   unsigned long long cls_cells[32];  // band cells per class (+ rerun slot)
+  // lane-cells a class's kernel stepped through (every lane of a wave over
+  // the wave's column span of each row, padding and finished lanes
+  // included): the work behind cls_cells
+  unsigned long long work_cells[32];
 };
 
 // One request of a serving batch (see k_assemble).

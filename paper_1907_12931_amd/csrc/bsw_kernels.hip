@@ -806,7 +806,8 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         bsw_diag* __restrict__ diag, uint32_t* tile_ctr, const Status* st,
         uint32_t* __restrict__ qtiles, PairDesc* __restrict__ ovf,
         long long* __restrict__ ovf_count, int persist, int RC,
-        unsigned long long* __restrict__ cls_cells) {
+        unsigned long long* __restrict__ cls_cells,
+        unsigned long long* __restrict__ work_cells) {
   if (st->bad) return;
   using CK = Chunk<WB>;
   using T = typename CK::T;
@@ -822,6 +823,7 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
   const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
   uint32_t tile = blockIdx.x;
   unsigned long long tile_cells_acc = 0;
+  unsigned long long span_chunks = 0;  // chunks stepped, summed over rows
   for (;;) {
     if (persist) {
       uint32_t v = 0;
@@ -946,6 +948,7 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
       const int c0 = wave_min(live ? (beg >> 2) : 0x7fffffff);
       const int cf = wave_min(live ? (rend >> 2) : 0x7fffffff);
       const int c1 = wave_max(live ? ((rend + 3) >> 2) : 0);
+      if (c1 > c0) span_chunks += (unsigned)(c1 - c0);
       int mkey = 0;
       // 8-bit unmasked chunks keep the row maximum per chunk: the largest
       // chunk maximum and the last chunk that reached it
@@ -1121,7 +1124,397 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
   }
   tile_cells_acc = wave_sum64(tile_cells_acc);
   if (lane == 0 && tile_cells_acc) atomicAdd(cls_cells, tile_cells_acc);
+  if (lane == 0 && span_chunks) atomicAdd(work_cells, span_chunks * 4ull * 64ull);
 #undef COL
+}
+
+// ---------------------------------------------------------------------------
+// Lane mode with the row buffer in registers (the main kernel: 8-bit
+// records, queries up to CAP).
+//
+// The inter-task scheme of Sec. 5.3: every lane owns one pair and the wave
+// walks rows in lock step, the same four-column chunk in every lane.  The
+// whole row of (H, E) byte records, CAP + 1 columns, lives in the lane's
+// vector registers (two dwords per chunk) and the pair's query codes too
+// (one dword per chunk), so the cell loop touches no memory.  The loop over
+// chunks is unrolled: chunk k always lives in the same registers, and a
+// row visits the wave's chunk span [c0, c1) by uniform branches.
+//
+// Lanes whose band starts inside or after a visited chunk read the columns
+// left of their band as zero (R7: H = F = 0 there), which keeps every value
+// flowing into the band start at zero.  Lanes whose band ends inside or
+// before a chunk read the columns at or past their end as zero and keep
+// their stored records there, except that column end takes H(i, end - 1)
+// (R8).  Neither kind of masked column can raise the row maximum: left of
+// the band every H is 0, and past the end H = F < H(i, end - 1).
+//
+// The row maximum and its column come from 16-bit keys H * 256 + j (the
+// larger column wins ties, R15), formed by a saturating multiply-add: a key
+// saturates at 0xffff exactly when H >= 256, so best >= 255 flags every pair
+// whose values may not fit a byte; those pairs are queued for the 32-bit
+// rerun (best + max(0, A - o_del - e_del) >= 255).
+//
+// The band shrink needs each lane's records at its own band edges, which
+// registers cannot be indexed by; a one-byte mirror per column in LDS
+// (H | E of the stored record: zero iff the column is empty) serves those
+// reads and the query-end score, whose column-end byte is H(i, end - 1).
+
+// key = H * 256 + j of two columns, saturated at 0xffff (v_pk_mad_u16 with
+// clamp); k256 holds 256 in both halves
+__device__ __forceinline__ uint32_t row_keys(uint32_t h2, uint32_t k256, uint32_t jj) {
+  uint32_t k;
+  asm("v_pk_mad_u16 %0, %1, %2, %3 clamp" : "=v"(k) : "v"(h2), "v"(k256), "s"(jj));
+  return k;
+}
+
+// Mask of a record dword (two 16-bit records) that clears its first n
+// records (n <= 0: none, n >= 2: both).
+__device__ __forceinline__ uint32_t rec_keep_from(int n) {
+  return n <= 0 ? ~0u : (n == 1 ? 0xffff0000u : 0u);
+}
+// Mask of a dword that clears its first n bytes (n <= 0: none, n >= 4: all).
+__device__ __forceinline__ uint32_t byte_keep_from(int n) {
+  return n >= 4 ? 0u : (~0u << (8 * imax(n, 0)));
+}
+__device__ __forceinline__ uint32_t usubsat16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
+                                          __builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t uaddsat16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(
+                                          __builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t umax16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
+
+// Byte c of the result is nonzero iff record c of the chunk (H and E bytes
+// of column 4k + c) is nonzero.
+__device__ __forceinline__ uint32_t chunk_nonzero(const uint2 r) {
+  const uint32_t h = __builtin_amdgcn_perm(r.y, r.x, 0x06040200u);
+  const uint32_t e = __builtin_amdgcn_perm(r.y, r.x, 0x07050301u);
+  return h | e;
+}
+
+// The four cells of a chunk in packed 16-bit arithmetic (as chunk_cells_pk)
+// returning the chunk's four H(i, j) values as two packed pairs.
+template <bool SYM>
+__device__ __forceinline__ uint2 chunk_cells_h(const uint2 ch, uint32_t sc, int& hl, int& f,
+                                               uint32_t& h01, uint32_t& h23,
+                                               const PkParams& pp) {
+  const s16x2 D01 = pk(__builtin_amdgcn_perm(0u, ch.x, 0x0c020c00u));
+  const s16x2 E01 = pk(__builtin_amdgcn_perm(0u, ch.x, 0x0c030c01u));
+  const s16x2 D23 = pk(__builtin_amdgcn_perm(0u, ch.y, 0x0c020c00u));
+  const s16x2 E23 = pk(__builtin_amdgcn_perm(0u, ch.y, 0x0c030c01u));
+  const uint32_t sc8 = sc << 8;
+  const s16x2 S01 = pk(__builtin_amdgcn_perm(sc8, sc, 0x08010a00u));
+  const s16x2 S23 = pk(__builtin_amdgcn_perm(sc8, sc, 0x09030b02u));
+  const s16x2 G01 = pmin(D01 + S01, D01 << 7), G23 = pmin(D23 + S23, D23 << 7);
+  const s16x2 TD01 = G01 - pp.oeD, TD23 = G23 - pp.oeD;
+  const s16x2 EN01 = pmax(psubsat(E01, pp.eD), TD01);
+  const s16x2 EN23 = pmax(psubsat(E23, pp.eD), TD23);
+  const s16x2 z = bcast(0);
+  const s16x2 A01 = pmax(SYM ? TD01 : G01 - pp.oeI, z);
+  const s16x2 A23 = pmax(SYM ? TD23 : G23 - pp.oeI, z);
+  const s16x2 F12 = pmax(pmax(A01, bcast(A01[0]) - pp.eI), bcast(f) - pp.eI12);
+  const s16x2 F34 = pmax(pmax(A23, bcast(A23[0]) - pp.eI), bcast(F12[1]) - pp.eI12);
+  const s16x2 F01 = (s16x2){(short)f, F12[0]}, F23 = (s16x2){F12[1], F34[0]};
+  const s16x2 H01 = pmax(pmax(G01, E01), F01), H23 = pmax(pmax(G23, E23), F23);
+  const uint32_t hx = __builtin_amdgcn_perm(unpk(H01), (uint32_t)hl, 0x05040100u);
+  const uint32_t x = __builtin_amdgcn_perm(unpk(EN01), hx, 0x06020400u);
+  const uint32_t hy = __builtin_amdgcn_perm(unpk(H23), unpk(H01), 0x0c040c02u);
+  const uint32_t y = __builtin_amdgcn_perm(unpk(EN23), hy, 0x06020400u);
+  h01 = unpk(H01);
+  h23 = unpk(H23);
+  hl = H23[1];
+  f = F34[1];
+  return make_uint2(x, y);
+}
+
+// Per-row state of the chunk sweep (uniform chunk bounds, the lane's band,
+// its score row, and the values carried along the row).
+struct RowSweep {
+  int c0, cb, cf, c1;  // wave-uniform
+  int beg, end;
+  uint32_t lo, hi;
+  int hl, f;
+  uint32_t mkey;       // packed row-maximum keys
+};
+
+// One row over chunks K .. NCH-1 of the register row (compile-time chunk
+// indices, so that r[] and qv[] stay in registers): chunks outside
+// [c0, c1) are skipped by uniform branches.
+template <int K, int NCH, int NQW, bool QNIB, bool SYM>
+__device__ __forceinline__ void sweep_chunks(uint2 (&r)[NCH], const uint32_t (&qv)[NQW],
+                                             uint32_t* mir, const PkParams& pp, RowSweep& w) {
+  if constexpr (K < NCH) {
+    if (K >= w.c1) return;
+    if (K >= w.c0) {
+      const uint2 orig = r[K];
+      uint2 in = orig;
+      if (K <= w.cb) {
+        // columns left of the band read as zero
+        const int nl = w.beg - 4 * K;  // records to clear, from the left
+        in.x &= rec_keep_from(nl);
+        in.y &= rec_keep_from(nl - 2);
+      }
+      if (K >= w.cf) {
+        // columns at or past the band end read as zero
+        const int n = w.end - 4 * K;   // records to keep, from the left
+        in.x &= ~rec_keep_from(n);
+        in.y &= ~rec_keep_from(n - 2);
+      }
+      // the chunk's four query codes (the right-edge chunk has none)
+      uint32_t qc = 0;
+      if constexpr (QNIB) {
+        if constexpr (K / 2 < NQW)
+          qc = ((K & 1) ? qv[K / 2] >> 4 : qv[K / 2]) & 0x0f0f0f0fu;
+      } else {
+        if constexpr (K < NQW) qc = qv[K];
+      }
+      const uint32_t sc = __builtin_amdgcn_perm(w.hi, w.lo, qc);
+      uint32_t h01, h23;
+      uint2 res = chunk_cells_h<SYM>(in, sc, w.hl, w.f, h01, h23, pp);
+      constexpr uint32_t J01 = (uint32_t)(4 * K) | ((uint32_t)(4 * K + 1) << 16);
+      constexpr uint32_t J23 = (uint32_t)(4 * K + 2) | ((uint32_t)(4 * K + 3) << 16);
+      const uint32_t k01 = row_keys(h01, 0x01000100u, J01);
+      const uint32_t k23 = row_keys(h23, 0x01000100u, J23);
+      w.mkey = umax16x2(w.mkey, umax16x2(k01, k23));
+      if (K >= w.cf) {
+        // keep the stored records at and past the end, except the H byte
+        // of column end, which takes H(i, end - 1) (R8)
+        const int nb = 2 * (w.end - 4 * K) + 1;  // bytes written, from the left
+        const uint32_t mx = ~byte_keep_from(nb), my = ~byte_keep_from(nb - 4);
+        res = make_uint2((res.x & mx) | (orig.x & ~mx), (res.y & my) | (orig.y & ~my));
+      }
+      r[K] = res;
+      mir[K * 64] = chunk_nonzero(res);
+    }
+    sweep_chunks<K + 1, NCH, NQW, QNIB, SYM>(r, qv, mir, pp, w);
+  }
+}
+
+template <int CAP> struct LaneVRegs {
+  // waves per SIMD the register budget is set for
+  static constexpr int WAVES = 2;
+};
+
+template <int CAP, bool SYM>
+__global__ void __launch_bounds__(64, LaneVRegs<CAP>::WAVES)
+k_lanev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
+        const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
+        const KParams* __restrict__ kp, bsw_result* __restrict__ out,
+        bsw_diag* __restrict__ diag, uint32_t* tile_ctr, const Status* st,
+        PairDesc* __restrict__ ovf, long long* __restrict__ ovf_count, int persist,
+        unsigned long long* __restrict__ cls_cells,
+        unsigned long long* __restrict__ work_cells) {
+  if (st->bad) return;
+  constexpr int NQ = CAP / 4;   // chunks holding query columns
+  constexpr int NCH = NQ + 1;   // and the chunk of the right-edge column CAP
+  constexpr bool QNIB = CAP > 64;             // query codes as nibbles
+  constexpr int NQW = QNIB ? NQ / 2 : NQ;     // words of query codes
+  extern __shared__ __align__(16) uint32_t mirror[];  // [NCH][64] nonzero bytes
+  const int lane = threadIdx.x;
+  uint32_t* mir = mirror + lane;
+#define MIRB(x) (((const uint8_t*)(mir + ((x) >> 2) * 64))[(x) & 3])
+  const long long begin = range[0], count = range[1];
+  const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
+  uint32_t tile = blockIdx.x;
+  unsigned long long tile_cells_acc = 0, span_chunks = 0;
+  uint2 r[NCH];
+  uint32_t qv[NQW];
+  for (;;) {
+    if (persist) {
+      uint32_t v = 0;
+      if (lane == 0) v = atomicAdd(tile_ctr, 1u);
+      tile = wave_first(__shfl(v, 0));
+    }
+    if (tile >= ntiles) break;
+    const long long kk = (long long)tile * 64 + lane;
+    const bool valid = kk < count;
+    PairDesc pd;
+    if (valid) {
+      pd = desc[begin + kk];
+    } else {
+      pd.qo = pd.to = 0;
+      pd.ql = pd.tl = 0;
+      pd.h0 = 1;
+      pd.idx = 0;
+      pd.pid = 0;
+    }
+    const KParams& P = kp[pd.pid];
+    const int Lq = pd.ql, Lt = valid ? pd.tl : 0, h0 = pd.h0;
+    const int oD = P.o_del, eD = P.e_del, oI = P.o_ins, eI = P.e_ins;
+    const PkParams pp = {bcast(eD), bcast(P.oe_del), bcast(SYM ? P.oe_del : P.oe_ins),
+                         bcast(eI), (s16x2){(short)eI, (short)(2 * eI)}};
+    const int zd = P.zdrop;
+    const int wb = band_cap(P, Lq);
+    const uint2* srow = (const uint2*)P.prow;  // score row of each target code
+    // query codes: aligned words that hold at least one query byte (never
+    // past the word of the last byte), byte-aligned to the query start;
+    // chunk c's four codes are byte-aligned word c, kept whole for short
+    // classes and as nibbles of a shared word (chunks 2m and 2m+1) otherwise
+    {
+      const uintptr_t qa = (uintptr_t)(q + pd.qo);
+      const uint32_t* qw = (const uint32_t*)(qa & ~(uintptr_t)3);
+      const uint32_t sh = (uint32_t)(qa & 3);
+      const int nw = Lq > 0 ? ((int)sh + Lq + 3) >> 2 : 0;
+      uint32_t w0 = nw > 0 ? qw[0] : 0u;
+#pragma unroll
+      for (int m = 0; m < NQW; ++m) {
+        if constexpr (QNIB) {
+          const uint32_t w1 = 2 * m + 1 < nw ? qw[2 * m + 1] : 0u;
+          const uint32_t w2 = 2 * m + 2 < nw ? qw[2 * m + 2] : 0u;
+          qv[m] = __builtin_amdgcn_alignbyte(w1, w0, sh) |
+                  (__builtin_amdgcn_alignbyte(w2, w1, sh) << 4);
+          w0 = w2;
+        } else {
+          const uint32_t w1 = m + 1 < nw ? qw[m + 1] : 0u;
+          qv[m] = __builtin_amdgcn_alignbyte(w1, w0, sh);
+          w0 = w1;
+        }
+      }
+    }
+    // first row of Eq. (3) in every column: H(-1, j-1) = max(0, h0 - o_ins -
+    // e_ins*j) (h0 itself at column 0), E = 0, in packed 16-bit pairs: the
+    // cost o_ins + e_ins*j saturates at 0xffff, above every 8-bit h0, so the
+    // saturating difference is exact.  Columns past the query end are never
+    // read (they lie past every band end) and need no clearing.
+    {
+      const uint32_t hh = (uint32_t)h0 | ((uint32_t)h0 << 16);
+      const uint32_t e4 = (uint32_t)(4 * eI) | ((uint32_t)(4 * eI) << 16);
+      uint32_t c01 = (uint32_t)imin(oI, 65535) | ((uint32_t)imin(oI + eI, 65535) << 16);
+      uint32_t c23 = (uint32_t)imin(oI + 2 * eI, 65535) |
+                     ((uint32_t)imin(oI + 3 * eI, 65535) << 16);
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        uint32_t x = usubsat16x2(hh, c01), y = usubsat16x2(hh, c23);
+        if (c == 0) x = (x & 0xffff0000u) | (uint32_t)h0;
+        r[c] = make_uint2(x, y);
+        mir[c * 64] = __builtin_amdgcn_perm(y, x, 0x06040200u);
+        c01 = uaddsat16x2(c01, e4);
+        c23 = uaddsat16x2(c23, e4);
+      }
+    }
+
+    int best = h0, bi = -1, bj = -1, gbest = -1, gi = -1, moff = 0;
+    int beg = 0, end = Lq, rows = 0, stop = 0;
+    long long cells = 0;
+    bool live = valid && Lt > 0;
+    const uint8_t* ts = t + pd.to;
+    // target code of the next row, loaded one row ahead
+    uint32_t tnext = live ? ts[0] : 0u;
+    for (int i = 0;; ++i) {
+      live = live && i < Lt;
+      if (__ballot(live) == 0) break;
+      const uint32_t tb = tnext;
+      if (live && i + 1 < Lt) tnext = ts[i + 1];
+      int hl = 0, f = 0;
+      uint32_t lo = 0, hi = 0;
+      if (live) {
+        ++rows;
+        // band (Sec. 5.1 (a)); columns left of beg are read as zero below
+        beg = imax(beg, i - wb);
+        end = imin(imin(end, i + wb + 1), Lq);
+        if (end > beg) cells += end - beg;
+        // the score row of this target base (a small table every lane reads
+        // from cache; loaded once per row)
+        const uint2 sr = srow[tb];
+        lo = sr.x;
+        hi = sr.y;
+        hl = beg == 0 ? imax(0, h0 - oD - eD * (i + 1)) : 0;
+      }
+      // chunk span of the live lanes: [c0, c1) is visited; chunks <= cb hold
+      // some lane's band start (or lie left of it), chunks >= cf some lane's
+      // band end (column end itself included)
+      const int c0 = wave_min(live ? (beg >> 2) : 0x7fffffff);
+      const int cb = wave_max(live ? (beg >> 2) : -1);
+      const int cf = wave_min(live ? (end >> 2) : 0x7fffffff);
+      const int c1 = wave_max(live ? (end >> 2) + 1 : 0);
+      span_chunks += (unsigned)(c1 - c0);
+      RowSweep sw;
+      sw.c0 = c0;
+      sw.cb = cb;
+      sw.cf = cf;
+      sw.c1 = c1;
+      sw.beg = beg;
+      sw.end = end;
+      sw.lo = lo;
+      sw.hi = hi;
+      sw.hl = hl;
+      sw.f = f;
+      sw.mkey = 0;
+      sweep_chunks<0, NCH, NQW, QNIB, SYM>(r, qv, mir, pp, sw);
+      const uint32_t mkey = sw.mkey;
+      if (live) {
+        // best score touching the end of the query (Sec. 5.4 (b)): the
+        // stored H(i, end - 1) at column end
+        if (imax(beg, end) == Lq) {
+          const int hend = MIRB(end);
+          gi = hend >= gbest ? i : gi;
+          gbest = imax(gbest, hend);
+        }
+        const uint32_t mk = imax((int)(mkey & 0xffffu), (int)(mkey >> 16));
+        const int m = (int)(mk >> 8), mj = (int)(mk & 0xffu);
+        if (m == 0) {
+          stop = 1;
+          live = false;
+        } else if (m > best) {
+          best = m;
+          bi = i;
+          bj = mj;
+          moff = imax(moff, mj > i ? mj - i : i - mj);
+        } else if (zd > 0) {
+          const int drift = (i - bi) - (mj - bj);
+          const int drop = best - m - (drift > 0 ? drift * eD : -drift * eI);
+          if (drop > zd) {
+            stop = 2;
+            live = false;
+          }
+        }
+        if (live) {
+          // shrink the band by its empty ends (Sec. 5.1 (c))
+          while (beg < end && MIRB(beg) == 0) ++beg;
+          int x = end;
+          while (x >= beg && MIRB(x) == 0) --x;
+          end = imin(x + 2, Lq);
+        }
+      }
+    }
+    unsigned long long my_cells = 0;
+    if (valid) {
+      const int slack = P.amax - P.oe_del > 0 ? P.amax - P.oe_del : 0;
+      if (best + slack >= 255) {
+        // some value may have needed more than a byte: rerun wider
+        const unsigned long long pos = atomicAdd((unsigned long long*)ovf_count, 1ull);
+        ovf[pos] = pd;
+      } else {
+        my_cells = (unsigned long long)cells;
+        bsw_result res;
+        res.score = best;
+        res.qle = bj + 1;
+        res.tle = bi + 1;
+        res.gtle = gi + 1;
+        res.gscore = gbest;
+        res.max_off = moff;
+        out[pd.idx] = res;
+        if (diag) {
+          bsw_diag dg;
+          dg.rows = rows;
+          dg.stop = stop;
+          dg.cells = cells;
+          diag[pd.idx] = dg;
+        }
+      }
+    }
+    tile_cells_acc += my_cells;
+    if (!persist) break;
+  }
+  tile_cells_acc = wave_sum64(tile_cells_acc);
+  if (lane == 0 && tile_cells_acc) atomicAdd(cls_cells, tile_cells_acc);
+  if (lane == 0 && span_chunks) atomicAdd(work_cells, span_chunks * 4ull * 64ull);
+#undef MIRB
 }
 
 // One pair per wave (the reruns of pairs whose values need more than their
@@ -1320,13 +1713,17 @@ static int cls_cap(int cls) {
   return LW_CAP[cls - CLS_W32];
 }
 
-// chunked classes (8-bit and 16-bit records) vs the legacy 32-bit kernel
-static bool chunked(int cls) { return cls < CLS_W32; }
+// register-row classes (8-bit records), chunked classes with an LDS ring
+// (16-bit records) and the 32-bit kernel with a private LDS row
+static bool regrow(int cls) { return cls < CLS_W16; }
+static bool chunked(int cls) { return cls >= CLS_W16 && cls < CLS_W32; }
 static int rec_bytes(int cls) { return cls < CLS_W16 ? 8 : 16; }
 
-// LDS bytes per wave of a class (chunked classes: without a ring)
+// LDS bytes per wave of a class (register-row classes: the nonzero-byte
+// mirror; chunked classes: without a ring)
 size_t lane_lds_per_wave(int cls) {
   const int cap = cls_cap(cls);
+  if (regrow(cls)) return (size_t)(cap / 4 + 1) * 64 * 4;
   if (chunked(cls)) return (size_t)(cap / 4 + 1) * 64 * rec_bytes(cls);
   return (size_t)(cap + 1) * 64 * 8 + (size_t)cap * 64;
 }
@@ -1334,10 +1731,10 @@ size_t lane_lds_per_wave(int cls) {
 // LDS bytes per 64-lane chunk row of a chunked class
 size_t lane_chunk_row_bytes(int cls) { return (size_t)64 * rec_bytes(cls); }
 
-// waves per workgroup: chunked classes run one wave per group; the 32-bit
-// kernel as many as fit in 64 KiB of LDS (1..4)
+// waves per workgroup: register-row and chunked classes run one wave per
+// group; the 32-bit kernel as many as fit in 64 KiB of LDS (1..4)
 int lane_waves_per_block(int cls) {
-  if (chunked(cls)) return 1;
+  if (regrow(cls) || chunked(cls)) return 1;
   const size_t b = lane_lds_per_wave(cls);
   int w = (int)(65536 / b);
   return w < 1 ? 1 : (w > 4 ? 4 : w);
@@ -1349,22 +1746,29 @@ typedef void (*LaneFn)(const PairDesc*, const long long*, const uint8_t*,
 typedef void (*LaneCFn)(const PairDesc*, const long long*, const uint8_t*,
                         const uint8_t*, const KParams*, bsw_result*, bsw_diag*,
                         uint32_t*, const Status*, uint32_t*, PairDesc*, long long*, int,
-                        int, unsigned long long*);
+                        int, unsigned long long*, unsigned long long*);
+
+typedef void (*LaneVFn)(const PairDesc*, const long long*, const uint8_t*,
+                        const uint8_t*, const KParams*, bsw_result*, bsw_diag*,
+                        uint32_t*, const Status*, PairDesc*, long long*, int,
+                        unsigned long long*, unsigned long long*);
+
+static LaneVFn lanev_fn(int cls, bool sym) {
+  static const LaneVFn tab8[2][NL8] = {
+      {k_lanev<32, false>, k_lanev<64, false>, k_lanev<96, false>, k_lanev<128, false>,
+       k_lanev<160, false>, k_lanev<192, false>, k_lanev<224, false>, k_lanev<256, false>},
+      {k_lanev<32, true>, k_lanev<64, true>, k_lanev<96, true>, k_lanev<128, true>,
+       k_lanev<160, true>, k_lanev<192, true>, k_lanev<224, true>, k_lanev<256, true>}};
+  return tab8[sym ? 1 : 0][cls - CLS_L8];
+}
 
 static LaneCFn lanec_fn(int cls, bool sym) {
-  static const LaneCFn tab8[2][NL8] = {
-      {k_lanec<32, false, 8>, k_lanec<64, false, 8>, k_lanec<96, false, 8>,
-       k_lanec<128, false, 8>, k_lanec<160, false, 8>, k_lanec<192, false, 8>,
-       k_lanec<224, false, 8>, k_lanec<256, false, 8>},
-      {k_lanec<32, true, 8>, k_lanec<64, true, 8>, k_lanec<96, true, 8>,
-       k_lanec<128, true, 8>, k_lanec<160, true, 8>, k_lanec<192, true, 8>,
-       k_lanec<224, true, 8>, k_lanec<256, true, 8>}};
   static const LaneCFn tab16[2][NLW] = {
       {k_lanec<32, false, 16>, k_lanec<64, false, 16>, k_lanec<128, false, 16>,
        k_lanec<256, false, 16>},
       {k_lanec<32, true, 16>, k_lanec<64, true, 16>, k_lanec<128, true, 16>,
        k_lanec<256, true, 16>}};
-  return cls < CLS_W16 ? tab8[sym ? 1 : 0][cls - CLS_L8] : tab16[sym ? 1 : 0][cls - CLS_W16];
+  return tab16[sym ? 1 : 0][cls - CLS_W16];
 }
 
 static LaneFn lanew_fn(int cls, bool persist) {
@@ -1379,6 +1783,7 @@ static LaneFn lanew_fn(int cls, bool persist) {
 // kernel symbol of a class (for chunked classes "flag" selects the
 // symmetric-gap variant, for the 32-bit kernel the persistent one)
 static const void* lane_sym(int cls, bool flag) {
+  if (regrow(cls)) return (const void*)lanev_fn(cls, flag);
   return chunked(cls) ? (const void*)lanec_fn(cls, flag) : (const void*)lanew_fn(cls, flag);
 }
 
@@ -1472,13 +1877,18 @@ void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,
                  const KParams* kp, bsw_result* out, bsw_diag* diag,
                  uint32_t* tile_ctr, const Status* st, uint32_t* qtiles,
                  PairDesc* ovf, long long* ovf_count, int ring, bool sym,
-                 unsigned long long* cls_cells, hipStream_t s) {
+                 unsigned long long* cls_cells, unsigned long long* work_cells,
+                 hipStream_t s) {
   const int wpb = lane_waves_per_block(cls);
-  if (chunked(cls))
+  if (regrow(cls))
+    hipLaunchKernelGGL(lanev_fn(cls, sym), dim3(blocks), dim3(64), lane_lds_per_wave(cls), s,
+                       desc, range, q, t, kp, out, diag, tile_ctr, st, ovf, ovf_count,
+                       persist ? 1 : 0, cls_cells, work_cells);
+  else if (chunked(cls))
     hipLaunchKernelGGL(lanec_fn(cls, sym), dim3(blocks), dim3(64),
                        (size_t)ring * lane_chunk_row_bytes(cls), s, desc, range, q, t, kp,
                        out, diag, tile_ctr, st, qtiles, ovf, ovf_count, persist ? 1 : 0,
-                       ring, cls_cells);
+                       ring, cls_cells, work_cells);
   else
     hipLaunchKernelGGL(lanew_fn(cls, persist), dim3(blocks), dim3(wpb * 64),
                        lane_lds_per_wave(cls) * wpb, s, desc, range, q, t, kp, out, diag,

@@ -115,6 +115,11 @@ int ctx_num_cu(const bsw_ctx* c);
 // Mark the context as having an asynchronous call in flight on s whose
 // completion is checked by done (bsw_ctx_wait calls it).
 void ctx_set_pending(bsw_ctx* c, hipStream_t s, int (*done)(bsw_ctx*));
+// BSW_EBUSY (with the message set) while an asynchronous call is pending:
+// every entry point that enqueues work on a context checks this first, so
+// that a new call never rewrites the pinned tables, status or graph that the
+// pending call's queued work still reads.
+int ctx_check_idle(const bsw_ctx* c);
 
 // Kind of the calls enqueued from now on (the shape they use and the tune
 // cache entry it comes from).

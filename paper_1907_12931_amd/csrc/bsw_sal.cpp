@@ -100,6 +100,7 @@ int bsw_sa_lookup_device(bsw_ctx* c, const int64_t* sa, uint64_t sa_len,
                          int64_t* out_pos, uint64_t out_cap, uint64_t* total, void* stream,
                          int32_t async) {
   if (!c) return set_error(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
   if (n < 0 || n > 0x7fffffffLL)
     return set_error(BSW_EINVAL, "n = %lld out of range", (long long)n);
   if (n == 0) {

@@ -216,6 +216,7 @@ int check_device_args(bsw_ctx* c, const uint8_t* reads, uint64_t reads_len,
                       uint64_t ref_len, const bsw_seed* seeds, int64_t n,
                       const bsw_seed_result* out) {
   if (!c) return set_error(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
   if (n < 0 || n > 0x7fffffffLL)
     return set_error(BSW_EINVAL, "n = %lld out of range", (long long)n);
   if (n == 0) return BSW_OK;
@@ -303,6 +304,8 @@ int bsw_extend_seeds(bsw_ctx* c, const uint8_t* reads, const uint64_t* read_off,
                      const bsw_seed* seeds, int64_t n, const bsw_params* params,
                      bsw_seed_result* out) {
   if (!c) return set_error(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
+  if (int rc0 = ctx_check_idle(c)) return rc0;
   if (n < 0 || n > 0x7fffffffLL)
     return set_error(BSW_EINVAL, "n = %lld out of range", (long long)n);
   if (n == 0) return BSW_OK;

@@ -136,3 +136,53 @@ def test_autotuner_keeps_results_and_caches_its_choice(oracle_lib, bsw, tmp_path
     assert c2.tune_info() == shape
     _same(bsw.outputs_to_numpy(out), want, "cached shape")
     c2.close()
+
+
+def test_async_call_blocks_the_context_until_waited(oracle_lib, bsw):
+    """A context holds one asynchronous call.  A second call before the wait
+    returns EBUSY and enqueues nothing (it would otherwise rewrite the
+    scoring table the first call's queued copy reads); calls that alternate
+    between two batches and two scoring sets recapture the graph each time
+    (the previous executable graph is destroyed only after its launch
+    finished) and every result matches the oracle."""
+    import torch
+    b1 = synth.batched_mix(n=40_000, seed=31)
+    b2 = synth.read_scale(n=30_000, seed=32)
+    other = [synth.scoring(2, -3, -1, 5, 2, w=100, zdrop=100, end_bonus=5)]
+    batches = {"b1": b1, "b2": b2}
+    sets = {"A": b1["scorings"], "B": other}
+    want = {(k, s): oracle_lib.extend_batch(b, sc)[0]
+            for k, b in batches.items() for s, sc in sets.items()}
+    devs = {k: bsw.to_device(b) for k, b in batches.items()}
+    outs = {k: bsw.alloc_outputs(len(b["h0"]))[0] for k, b in batches.items()}
+    stream = torch.cuda.Stream()
+    with bsw.Context() as ctx:
+        seq = [("b1", "A"), ("b2", "B"), ("b1", "B"), ("b2", "A"), ("b1", "A"),
+               ("b1", "B")]
+        for k, (name, sname) in enumerate(seq):
+            outs[name].fill_(0)
+            torch.cuda.synchronize()
+            ctx.extend_device(devs[name], sets[sname], outs[name], stream=stream,
+                              async_=True)
+            with pytest.raises(bsw.BswError) as ei:
+                ctx.extend_device(devs[name], sets["B" if sname == "A" else "A"],
+                                  outs[name])
+            assert ei.value.code == bsw.EBUSY
+            ctx.wait()
+            _same(bsw.outputs_to_numpy(outs[name]), want[name, sname], f"call {k}")
+
+
+@pytest.mark.parametrize("groups", [16, 96])
+def test_persistent_groups_take_many_tiles(oracle_lib, bsw, groups):
+    """Every class's persistent grid capped far below its tile count, so
+    each workgroup takes many tiles from the class queue in turn (tile
+    re-entry: the row buffer, query staging and per-pair state start over
+    for every tile); all fields and diagnostics equal the oracle's."""
+    b = synth.batched_mix(n=300_000, seed=88, workers=8)
+    want, wdiag = oracle_lib.extend_batch(b, b["scorings"])
+    for graph in (True, False):
+        with bsw.Context(max_groups=groups, graph=graph) as c:
+            got, gdiag = c.extend(b, with_diag=True)
+        _same(got, want, f"groups {groups} graph {graph}")
+        for f in ("rows", "stop", "cells"):
+            assert np.array_equal(gdiag[f], wdiag[f]), f"groups {groups}: diag {f}"
