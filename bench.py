@@ -31,9 +31,41 @@ sys.path.insert(0, ROOT)
 # for E, two subtracts + max3 for F, shift-or + max for the row maximum and
 # its column.
 OPS_PER_CELL = 12
-# MI355X: 256 CUs x 4 SIMD x 16 lanes = 64 int32 lane-ops per CU per clock,
-# 2.4 GHz peak engine clock
-PEAK_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X spec: 256 CUs x 4 SIMD x 16 lanes = 64 int32 lane-ops per CU per
+# clock at the 2.4 GHz peak engine clock; packed 16-bit instructions do two
+# operations per lane
+SPEC_PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
+SPEC_PEAK_PK16_TOPS = 2 * SPEC_PEAK_I32_TOPS
+
+
+def pack_of(cls):
+    """Operations per lane-instruction that a class's arithmetic can reach:
+    2 for 8- and 16-bit values (packed 16-bit instructions), 1 for 32-bit
+    values."""
+    return 2 if cls.startswith(("lane8", "lane16", "wave16")) else 1
+
+
+def host_cpu():
+    """(CPU model, logical CPUs this process may use)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return model, nproc
+
+
+def oracle_threads():
+    # every host CPU this process may use, at most the 16 of a one-GPU share
+    return max(1, min(16, host_cpu()[1]))
 
 
 def log(*a):
@@ -194,7 +226,7 @@ def seed_cpu_baseline(np, sw, seconds):
     """The reference seed driver on the host cores, on a random sample of the
     seeds sized for about `seconds` of work."""
     from oracle import seeds as oseeds
-    threads = min(16, os.cpu_count() or 1)
+    threads = oracle_threads()
     rng = np.random.default_rng(0)
     ns = len(sw["seeds"])
 
@@ -435,7 +467,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--pairs", type=int, default=4_000_000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-seeds", action="store_true",
                     help="skip the read-level seed driver leg")
@@ -452,6 +484,13 @@ def main():
                     help="run only the seed driver leg and print it as the JSON line "
                          "(for profiling it alone)")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the read-scale and wide-band workloads")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="run only the plain path of the main workload (no tuner) and "
+                         "print its timings (for counter profiles of the DP kernels)")
+    ap.add_argument("--peak-only", action="store_true",
+                    help="print the measured integer-VALU peaks and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shapes (skip the autotuner)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -477,7 +516,7 @@ def main():
         torch.bitwise_not(x, out=y)
         torch.cuda.synchronize()
         del x, y
-    workers = min(16, os.cpu_count() or 1)
+    workers = oracle_threads()
     if args.smem_only:
         w = synth.sa_workload(**synth.SA_BENCH)
         leg = smem_search(bsw, synth, torch, np, w, args.steps, args.warmup)
@@ -507,66 +546,46 @@ def main():
             leg["cpu_baseline"] = seed_cpu_baseline(np, sw, args.cpu_seconds)
         print(json.dumps(leg), flush=True)
         return
+    if args.peak_only:
+        print(json.dumps(valu_peaks(bsw)), flush=True)
+        return
     t0 = time.time()
     batch = synth.batched_mix(n=args.pairs, workers=workers)
     n = len(batch["h0"])
     log(f"generated {n} pairs in {time.time() - t0:.1f}s")
-    dev = bsw.to_device(batch)
-    out, diag = bsw.alloc_outputs(n, with_diag=True)
-    torch.cuda.synchronize()
-
     import tempfile
     tune_cache = os.path.join(tempfile.mkdtemp(prefix="bsw_tune_"), "tune.json")
-    tuned = {}
-
-    def run_path(path, steps, warmup, graph=True):
-        ctx = bsw.Context(path=path, graph=graph,
-                          tune_cache=tune_cache if path == bsw.PATH_BATCHED else None)
-        if path == bsw.PATH_BATCHED and not tuned and not args.no_tune:
-            # launch shapes from the autotuner, on this batch (untimed)
-            ms, shape = ctx.tune(dev, batch["scorings"], out, reps=4)
-            tuned.update(shape, tune_best_ms=round(ms, 3))
-            log(f"tuned: {tuned}")
-        ctx.extend_device(dev, batch["scorings"], out, diag)  # cells + warm
-        cells = int(diag.view(torch.int64).view(n, 2)[:, 1].sum().item())
-        for _ in range(warmup):
-            ctx.extend_device(dev, batch["scorings"], out)
-        torch.cuda.synchronize()
-        dp_ms, prep_ms, launches = [], [], 0
-        per_kernel = {}
-        t = time.perf_counter()
-        for _ in range(steps):
-            ctx.extend_device(dev, batch["scorings"], out)
-            tm = ctx.last_timing()
-            dp_ms.append(tm[2])
-            prep_ms.append(tm[1])
-            launches = int(tm[3])
-            for name, kc, kms in ctx.last_kernels():
-                per_kernel.setdefault(name, []).append((kc, kms))
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t) / steps
-        ctx.close()
-        kernels = {name: {"cells": int(np.mean([v[0] for v in vals])),
-                          "ms": float(np.mean([v[1] for v in vals]))}
-                   for name, vals in per_kernel.items()}
-        return {"cells": cells, "ms_per_step": wall * 1e3,
-                "dp_ms": float(np.mean(dp_ms)), "prep_ms": float(np.mean(prep_ms)),
-                "dp_launches": launches, "kernels": kernels}
-
-    # headline: the batched path as a graph replay (its kernels overlap on
-    # side streams, and a graph's inner steps carry no event timestamps)
-    b = run_path(bsw.PATH_BATCHED, args.steps, args.warmup)
+    if args.plain_only:
+        # one path alone (for counter profiles of the DP kernels)
+        leg = bsw_paths(bsw, torch, np, batch, args.steps, args.warmup, tune_cache,
+                        tune=False, batched=False)
+        print(json.dumps(strip(leg["plain"])), flush=True)
+        return
+    peaks = valu_peaks(bsw)
+    log(f"valu peaks: {peaks}")
+    main_leg = bsw_paths(bsw, torch, np, batch, args.steps, args.warmup, tune_cache,
+                         tune=not args.no_tune)
+    b, p = main_leg["batched"], main_leg["plain"]
     cells = b["cells"]
     gcups = cells / (b["ms_per_step"] / 1e3) / 1e9
-    log(f"batched (graph): {b}")
-    # the plain path runs one kernel at a time on one stream: its per-launch
-    # HIP events time each DP kernel alone
-    p = run_path(bsw.PATH_PLAIN, args.steps, args.warmup)
-    assert p["cells"] == cells
-    log(f"plain: {p}")
     plain = {"value": round(p["cells"] / (p["ms_per_step"] / 1e3) / 1e9, 2),
              "unit": "GCUPS", "ms_per_step": round(p["ms_per_step"], 3),
              "dp_ms": round(p["dp_ms"], 3), "dp_launches": p["dp_launches"]}
+    roofline = bsw_roofline(main_leg, peaks, batch["scorings"])
+    roofline["traffic"] = traffic_from_profile(roofline["kernel"], roofline["kernel_cells"])
+
+    # the other pair workloads at full size: read-scale reads (1,000,000
+    # pairs) and the wide-band stress batch (500,000 pairs, 32-bit values)
+    legs = {}
+    if not args.no_legs:
+        for name, gen, mb in (("read_scale", synth.read_scale, 0),
+                              ("wide_band", synth.wide_band, 32)):
+            t0 = time.time()
+            wb = gen(workers=workers)
+            log(f"generated {name}: {len(wb['h0'])} pairs in {time.time() - t0:.1f}s")
+            lg = bsw_paths(bsw, torch, np, wb, args.steps, args.warmup, tune_cache,
+                           tune=not args.no_tune, min_lane_bits=mb)
+            legs[name] = (wb, lg)
 
     serving = None
     if not args.no_serve:
@@ -595,48 +614,21 @@ def main():
                                     args.warmup, tune=not args.no_tune)
         log(f"seed driver: {seeds_leg}")
 
-    # dominant kernel: the DP launch with the largest device time; its
-    # algorithmic work is its settled cells x OPS_PER_CELL int32 operations
-    dom, dk = max(p["kernels"].items(), key=lambda kv: kv[1]["ms"])
-    achieved = dk["cells"] * OPS_PER_CELL / (dk["ms"] / 1e3) / 1e12
-    step = cells * OPS_PER_CELL / (b["ms_per_step"] / 1e3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3),
-                "peak": round(PEAK_INT_TOPS, 3), "unit": "TOP/s",
-                "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": None,
-                "kernel": f"{kernel_symbol(dom, batch['scorings'])} (class {dom})",
-                "kernel_ms": round(dk["ms"], 3),
-                "kernel_cells": dk["cells"], "ops_per_cell": OPS_PER_CELL,
-                "timed_on": "plain path (each DP kernel alone on one stream)",
-                "batched_step_achieved": round(step, 3),
-                "batched_step_frac": round(step / PEAK_INT_TOPS, 4),
-                "per_kernel_ms": {k: round(v["ms"], 3) for k, v in p["kernels"].items()
-                                  if v["cells"]},
-                "per_kernel_gcups": {k: round(v["cells"] / v["ms"] / 1e6, 1)
-                                     for k, v in p["kernels"].items() if v["cells"]}}
-    roofline["traffic"] = traffic_from_profile(roofline["kernel"], dk["cells"])
-
-    cpu = None
+    # the oracle on the host: timed on a sample of the batch, and its
+    # results compared with both GPU paths' results on every pair it ran
+    cpu = parity = None
     if not args.no_cpu:
-        import oracle
-        threads = min(16, os.cpu_count() or 1)
-        rng = np.random.default_rng(0)
-        # calibrate on a small sample, then time a sample sized for about
-        # --cpu-seconds of work
-        probe = synth.subset(batch, rng.choice(n, size=min(n, 20000), replace=False))
-        t = time.perf_counter()
-        _, pd = oracle.extend_batch(probe, batch["scorings"], n_threads=threads)
-        rate = len(probe["h0"]) / (time.perf_counter() - t)
-        m = int(min(n, max(20000, rate * args.cpu_seconds)))
-        idx = rng.choice(n, size=m, replace=False)
-        sample = synth.subset(batch, idx)
-        t = time.perf_counter()
-        _, sd = oracle.extend_batch(sample, batch["scorings"], n_threads=threads)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(int(sd["cells"].sum()) / dt / 1e9, 3), "unit": "GCUPS",
-               "cores": threads, "kind": "oracle",
-               "sample": f"{m} random pairs of the {n}-pair batch, "
-                         f"{int(sd['cells'].sum())} cells, {dt:.1f} s"}
-        log(f"cpu: {cpu}")
+        cpu, parity = cpu_leg(np, synth, batch, main_leg, args.cpu_seconds)
+        log(f"cpu: {cpu}; parity: {parity}")
+    extra = {}
+    for name, (wb, lg) in legs.items():
+        extra[name] = leg_summary(lg, peaks, wb)
+        if not args.no_cpu:
+            c, par = cpu_leg(np, synth, wb, lg, args.cpu_seconds / 3, per_core=False)
+            extra[name]["cpu_baseline"] = c
+            extra[name]["parity"] = par
+        log(f"{name}: {extra[name]}")
+    if not args.no_cpu:
         if seeds_leg is not None:
             seeds_leg["cpu_baseline"] = seed_cpu_baseline(np, sw, args.cpu_seconds)
             log(f"cpu seeds: {seeds_leg['cpu_baseline']}")
@@ -648,24 +640,226 @@ def main():
             smem_leg["cpu_baseline"] = smem_cpu_baseline(np, synth, sal_w, args.cpu_seconds)
             log(f"cpu smem search: {smem_leg['cpu_baseline']}")
 
+    bad = [k for k, v in [("batched_mix", parity)] +
+           [(k, v.get("parity")) for k, v in extra.items()] if v and v["mismatches"]]
     res = {
         "metric": "GCUPS (bit-exact vs oracle) batched vs plain; p50/p99 latency under serving",
-        "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
+        "value": None if bad else round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(b["ms_per_step"], 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "i16x2",
+        "data": "synthetic",
         "config": {"workload": f"batched_mix: {n} pairs, qlen 1-250 from "
                                "100/150/250 bp sources, tlen <= qlen+200, 20% z-drop, "
                                "match 1 mismatch -4 gap 6+k w 100 zdrop 100 bonus 5",
                    "pairs": n, "cells": cells, "path": "batched",
-                   "dp_launches": b["dp_launches"], "graph": True, "tuned": tuned,
-                   "prep_bin_ms": round(p["prep_ms"], 3)},
-        "plain": plain, "serving": serving, "seed_driver": seeds_leg, "sa_lookup": sal_leg,
+                   "arithmetic": "8-bit H/E records, packed 16-bit integer cell updates; "
+                                 "32-bit values for pairs whose score exceeds 8 bits",
+                   "dp_launches": b["dp_launches"], "graph": True, "tuned": main_leg["tuned"],
+                   "prep_bin_ms": round(p["prep_ms"], 3),
+                   "parity_checked_pairs": parity["checked_pairs"] if parity else 0},
+        "plain": plain, "parity": parity, "workloads": extra, "valu_peak": peaks,
+        "serving": serving, "seed_driver": seeds_leg, "sa_lookup": sal_leg,
         "fm_search": fm_leg, "smem_search": smem_leg,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+    if bad:
+        log(f"PARITY FAILURE on {bad}: no value reported")
+        sys.exit(1)
+
+
+def valu_peaks(bsw):
+    """Measured integer-VALU rates (TOP/s) of the device beside the spec:
+    i32 = the better of v_add_u32 and v_max3_i32 lane-instructions/s, pk16 =
+    the better of v_pk_add_u16 and v_pk_max_i16, two operations each."""
+    r = {k: round(bsw.valu_peak(k)[1] / 1e12, 3) for k in bsw.PEAK_KINDS}
+    return {"i32_tops": max(r["v_add_u32"], r["v_max3_i32"]),
+            "pk16_tops": max(r["v_pk_add_u16"], r["v_pk_max_i16"]),
+            "kinds_tops": r, "spec_i32_tops": round(SPEC_PEAK_I32_TOPS, 3),
+            "spec_pk16_tops": round(SPEC_PEAK_PK16_TOPS, 3)}
+
+
+def peak_for(cls, peaks):
+    return peaks["pk16_tops"] if pack_of(cls) == 2 else peaks["i32_tops"]
+
+
+def bsw_paths(bsw, torch, np, batch, steps, warmup, tune_cache, tune=True, batched=True,
+              min_lane_bits=0):
+    """Run a resident batch on the batched path (graph replays, tuned shape)
+    and on the plain path, each into its own output buffers.  Returns the
+    timings, per-launch cells and work, and both paths' results on the
+    host."""
+    n = len(batch["h0"])
+    dev = bsw.to_device(batch)
+    torch.cuda.synchronize()
+    tuned = {}
+
+    def run_path(path, graph=True):
+        out, diag = bsw.alloc_outputs(n, with_diag=True)
+        ctx = bsw.Context(path=path, graph=graph, min_lane_bits=min_lane_bits,
+                          tune_cache=tune_cache if path == bsw.PATH_BATCHED else None)
+        if path == bsw.PATH_BATCHED and tune:
+            # launch shapes from the autotuner, on this batch (untimed)
+            ms, shape = ctx.tune(dev, batch["scorings"], out, reps=3)
+            tuned.update(shape, tune_best_ms=round(ms, 3))
+            log(f"tuned: {tuned}")
+        ctx.extend_device(dev, batch["scorings"], out, diag)  # cells + warm
+        cells = int(diag.view(torch.int64).view(n, 2)[:, 1].sum().item())
+        for _ in range(warmup):
+            ctx.extend_device(dev, batch["scorings"], out)
+        torch.cuda.synchronize()
+        dp_ms, prep_ms, launches = [], [], 0
+        per_kernel = {}
+        t = time.perf_counter()
+        for _ in range(steps):
+            ctx.extend_device(dev, batch["scorings"], out)
+            tm = ctx.last_timing()
+            dp_ms.append(tm[2])
+            prep_ms.append(tm[1])
+            launches = int(tm[3])
+            for (name, kc, kms), kw in zip(ctx.last_kernels(), ctx.last_work()):
+                per_kernel.setdefault(name, []).append((kc, kms, kw))
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / steps
+        ctx.close()
+        kernels = {name: {"cells": int(np.mean([v[0] for v in vals])),
+                          "ms": float(np.mean([v[1] for v in vals])),
+                          "work": int(np.mean([v[2] for v in vals]))}
+                   for name, vals in per_kernel.items()}
+        res, dg = bsw.outputs_to_numpy(out, diag)
+        del out, diag
+        return {"cells": cells, "ms_per_step": wall * 1e3,
+                "dp_ms": float(np.mean(dp_ms)), "prep_ms": float(np.mean(prep_ms)),
+                "dp_launches": launches, "kernels": kernels, "res": res, "diag": dg}
+
+    leg = {"tuned": tuned}
+    if batched:
+        leg["batched"] = run_path(bsw.PATH_BATCHED)
+        log(f"batched (graph): {strip(leg['batched'])}")
+    leg["plain"] = run_path(bsw.PATH_PLAIN)
+    log(f"plain: {strip(leg['plain'])}")
+    if batched:
+        assert leg["plain"]["cells"] == leg["batched"]["cells"]
+    del dev
+    return leg
+
+
+def strip(run):
+    return {k: v for k, v in run.items() if k not in ("res", "diag")}
+
+
+def bsw_roofline(leg, peaks, scorings):
+    """Roofline of the dominant DP kernel (the plain-path launch with the
+    largest device time: there each kernel runs alone on one stream, timed
+    by HIP events on that stream) and of the whole batched step.  Work is
+    OPS_PER_CELL operations per settled cell; the peak is the measured rate
+    of the kernel's arithmetic (packed 16-bit for 8/16-bit values)."""
+    b, p = leg["batched"], leg["plain"]
+    dom, dk = max(p["kernels"].items(), key=lambda kv: kv[1]["ms"])
+    achieved = dk["cells"] * OPS_PER_CELL / (dk["ms"] / 1e3) / 1e12
+    peak = peak_for(dom, peaks)
+    # the batched step against the cell-weighted peak of its classes
+    roof_s = sum(v["cells"] * OPS_PER_CELL / (peak_for(k, peaks) * 1e12)
+                 for k, v in b["kernels"].items())
+    step = b["cells"] * OPS_PER_CELL / (b["ms_per_step"] / 1e3) / 1e12
+    step_peak = b["cells"] * OPS_PER_CELL / roof_s / 1e12 if roof_s else 0.0
+    useful = {k: round(v["cells"] / v["work"], 4) for k, v in p["kernels"].items()
+              if v["cells"] and v["work"]}
+    work = sum(v["work"] for v in p["kernels"].values() if v["work"])
+    counted = sum(v["cells"] for v in p["kernels"].values() if v["work"])
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "peak_kind": "measured, packed 16-bit" if pack_of(dom) == 2 else "measured, int32",
+            "peak_spec": round(SPEC_PEAK_PK16_TOPS if pack_of(dom) == 2 else
+                               SPEC_PEAK_I32_TOPS, 3),
+            "frac_spec": round(achieved / (SPEC_PEAK_PK16_TOPS if pack_of(dom) == 2 else
+                                           SPEC_PEAK_I32_TOPS), 4),
+            "kernel": f"{kernel_symbol(dom, scorings)} (class {dom})",
+            "kernel_ms": round(dk["ms"], 3),
+            "kernel_cells": dk["cells"], "ops_per_cell": OPS_PER_CELL,
+            "timed_on": "plain path (each DP kernel alone on one stream)",
+            "batched_step_achieved": round(step, 3),
+            "batched_step_peak": round(step_peak, 3),
+            "batched_step_frac": round(step / step_peak, 4) if step_peak else None,
+            "oracle_cells_per_gpu_work": round(counted / work, 4) if work else None,
+            "per_kernel_ms": {k: round(v["ms"], 3) for k, v in p["kernels"].items()
+                              if v["cells"]},
+            "per_kernel_gcups": {k: round(v["cells"] / v["ms"] / 1e6, 1)
+                                 for k, v in p["kernels"].items() if v["cells"]},
+            "per_kernel_useful": useful}
+
+
+def leg_summary(leg, peaks, batch):
+    b, p = leg["batched"], leg["plain"]
+    n = len(batch["h0"])
+    r = bsw_roofline(leg, peaks, batch["scorings"])
+    return {"value": round(b["cells"] / (b["ms_per_step"] / 1e3) / 1e9, 2), "unit": "GCUPS",
+            "pairs": n, "cells": b["cells"], "ms_per_step": round(b["ms_per_step"], 3),
+            "plain": round(p["cells"] / (p["ms_per_step"] / 1e3) / 1e9, 2),
+            "plain_ms_per_step": round(p["ms_per_step"], 3), "tuned": leg["tuned"],
+            "roofline": {k: r[k] for k in ("achieved", "peak", "frac", "kernel", "kernel_ms",
+                                           "batched_step_frac", "per_kernel_gcups",
+                                           "per_kernel_useful",
+                                           "oracle_cells_per_gpu_work")}}
+
+
+def cpu_leg(np, synth, batch, leg, seconds, per_core=True):
+    """The oracle on the host cores: a sample of the batch sized for about
+    `seconds` of work (every pair when that fits), three timed runs, the
+    median reported; then the GPU results of both paths are compared with
+    the oracle's on every sampled pair, all six fields and the diagnostics.
+    With per_core, a single-thread run on a length-stratified 1% subsample
+    gives the per-core rate."""
+    import oracle
+    model, nproc = host_cpu()
+    threads = oracle_threads()
+    n = len(batch["h0"])
+    rng = np.random.default_rng(0)
+    probe = synth.subset(batch, rng.choice(n, size=min(n, 20000), replace=False))
+    t = time.perf_counter()
+    oracle.extend_batch(probe, batch["scorings"], n_threads=threads)  # also the warm-up
+    rate = len(probe["h0"]) / (time.perf_counter() - t)
+    m = int(min(n, max(20000, rate * seconds / 3)))
+    idx = np.sort(rng.choice(n, size=m, replace=False)) if m < n else np.arange(n)
+    sample = synth.subset(batch, idx)
+    times, want = [], None
+    for _ in range(3):
+        t = time.perf_counter()
+        r = oracle.extend_batch(sample, batch["scorings"], n_threads=threads)
+        times.append(time.perf_counter() - t)
+        if want is None:
+            want = r
+    dt = float(np.median(times))
+    wcells = int(want[1]["cells"].sum())
+    cpu = {"value": round(wcells / dt / 1e9, 3), "unit": "GCUPS", "cores": threads,
+           "kind": "oracle", "cpu_model": model, "nproc": nproc,
+           "sample": f"{m} {'random ' if m < n else ''}pairs of the {n}-pair batch, "
+                     f"{wcells} cells, median of 3 runs {dt:.2f} s"}
+    if per_core:
+        # 1% of the pairs, stratified by query length (every 100th pair in
+        # query-length order), on one thread
+        ql = np.diff(batch["q_off"].astype(np.int64))
+        sub = np.sort(np.argsort(ql, kind="stable")[::100])
+        s1 = synth.subset(batch, sub)
+        t = time.perf_counter()
+        _, d1 = oracle.extend_batch(s1, batch["scorings"], n_threads=1)
+        t1 = time.perf_counter() - t
+        cpu["per_core_gcups"] = round(int(d1["cells"].sum()) / t1 / 1e9, 3)
+        cpu["per_core_sample"] = (f"{len(sub)} pairs (every 100th by query length), "
+                                  f"{int(d1['cells'].sum())} cells, 1 thread, {t1:.2f} s")
+    mism = 0
+    for path in ("batched", "plain"):
+        got, gd = leg[path]["res"][idx], leg[path]["diag"][idx]
+        for f in want[0].dtype.names:
+            mism += int(np.count_nonzero(got[f] != want[0][f]))
+        for f in want[1].dtype.names:
+            mism += int(np.count_nonzero(gd[f] != want[1][f]))
+    parity = {"checked_pairs": m, "paths": ["batched", "plain"],
+              "fields": list(want[0].dtype.names) + list(want[1].dtype.names),
+              "mismatches": mism}
+    return cpu, parity
 
 
 if __name__ == "__main__":

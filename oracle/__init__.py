@@ -122,6 +122,12 @@ def extend_batch(batch, scorings, n_threads: int = 0):
     if pid is not None:
         pid = np.ascontiguousarray(pid, dtype=np.uint8)
     n = len(h0)
+    if n_threads <= 0:
+        # the CPUs this process may use, at most 16 (a one-GPU host share)
+        try:
+            n_threads = min(16, len(os.sched_getaffinity(0)))
+        except AttributeError:
+            n_threads = min(16, os.cpu_count() or 1)
     params = (Params * len(scorings))(*[make_params(s) for s in scorings])
     out = np.zeros(n, dtype=RESULT_DTYPE)
     diag = np.zeros(n, dtype=DIAG_DTYPE)
