@@ -83,6 +83,11 @@ def lib():
             ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
             ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
             ctypes.c_void_p]
+        L.bsw_ref_extend_one_bits.restype = ctypes.c_int
+        L.bsw_ref_extend_one_bits.argtypes = [
+            ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+            ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -143,17 +148,19 @@ def extend_batch(batch, scorings, n_threads: int = 0):
     return out, diag
 
 
-def extend_one(q, t, h0, scoring):
-    """Convenience wrapper for a single pair given as code sequences."""
+def extend_one(q, t, h0, scoring, bits=32):
+    """Convenience wrapper for a single pair given as code sequences; bits
+    = 8 or 16 runs it in saturating lanes of that width."""
     q = np.ascontiguousarray(np.asarray(q, dtype=np.uint8))
     t = np.ascontiguousarray(np.asarray(t, dtype=np.uint8))
     out = np.zeros(1, dtype=RESULT_DTYPE)
     diag = np.zeros(1, dtype=DIAG_DTYPE)
     p = make_params(scoring)
-    rc = lib().bsw_ref_extend_one(
-        len(q), q.ctypes.data if len(q) else None, len(t),
-        t.ctypes.data if len(t) else None, int(h0), ctypes.byref(p),
-        out.ctypes.data, diag.ctypes.data)
+    args = (len(q), q.ctypes.data if len(q) else None, len(t),
+            t.ctypes.data if len(t) else None, int(h0), ctypes.byref(p),
+            out.ctypes.data, diag.ctypes.data)
+    rc = (lib().bsw_ref_extend_one(*args) if bits == 32
+          else lib().bsw_ref_extend_one_bits(*args, int(bits)))
     if rc != 0:
         raise OracleError(rc, 0)
     r = out[0]

@@ -27,6 +27,18 @@ row-scan rules of Sec. 5.4 (a)-(b) and R15:
 * per row, m = max over the row and mj = the largest column reaching it,
 * the best score moves only on a strict increase (earliest row wins),
 * the query-end score is H(i, Lq-1), taking the latest row on ties.
+
+``gated_cell_scores`` / ``extend_gated`` enumerate the same paths under the
+one extra rule that gives the method its zero floors and its positive-
+diagonal gate (reading R4 of Sec. 5.1 Eq. (2)): a path is only extended
+while its running score is positive, i.e. every proper prefix of a path
+(the seed, every aligned step and every step of a gap run) scores > 0, and
+a cell's score is max(0, best such path).  With a band wider than both
+sequences, a huge end bonus and z-drop off, this equals the method as long
+as its band shrink never cuts a row short on the right and the first
+column (the seed's deletion run) is zero once the band has left column 0;
+the method then stops at the first all-zero row, which ``extend_gated``
+takes from the cell scores as well.
 """
 from __future__ import annotations
 
@@ -99,3 +111,64 @@ def heuristic_free_scoring(base, qlen, tlen):
     sc["end_bonus"] = 10**6
     sc["zdrop"] = 0
     return sc
+
+
+def gated_cell_scores(q, t, h0, sc):
+    """Cell scores under the positive-prefix rule (see the module
+    docstring): max(0, best path whose proper prefixes all score > 0)."""
+    Lq, Lt = len(q), len(t)
+    S = np.asarray(sc["mat"], dtype=np.int64).reshape(5, 5)
+    oD, eD, oI, eI = sc["o_del"], sc["e_del"], sc["o_ins"], sc["e_ins"]
+    best = np.zeros((Lt, Lq), dtype=np.int64)
+    stack = [(-1, -1, h0, False)]
+    while stack:
+        i, j, s, after_run = stack.pop()
+        if i >= 0 and j >= 0 and s > best[i, j]:
+            best[i, j] = s
+        if s <= 0:
+            continue  # a path is not extended past a non-positive score
+        if i + 1 < Lt and j + 1 < Lq:
+            stack.append((i + 1, j + 1, s + S[t[i + 1], q[j + 1]], False))
+        if after_run:
+            continue
+        # a run of k steps: each of its first k-1 steps must stay positive
+        for k in range(1, Lq - j):
+            v = s - oI - k * eI
+            stack.append((i, j + k, v, True))
+            if v <= 0:
+                break
+        for k in range(1, Lt - i):
+            v = s - oD - k * eD
+            stack.append((i + k, j, v, True))
+            if v <= 0:
+                break
+    return best
+
+
+def extend_gated(q, t, h0, sc):
+    """Outputs of the method from ``gated_cell_scores``: rows are scanned up
+    to the first all-zero row (the method's all-zero abort), with the row
+    rules of Sec. 5.4 (a)-(b) and R15.  Only valid under the conditions in
+    the module docstring (checked by the caller)."""
+    q = list(int(x) for x in q)
+    t = list(int(x) for x in t)
+    Lq, Lt = len(q), len(t)
+    if Lt == 0:
+        return (h0, 0, 0, 0, -1, 0)
+    if Lq == 0:
+        return (h0, 0, 0, 1, max(0, h0 - sc["o_del"] - sc["e_del"]), 0)
+    H = gated_cell_scores(q, t, h0, sc)
+    best, bi, bj, gbest, gi, moff = h0, -1, -1, -1, -1, 0
+    for i in range(Lt):
+        row = H[i]
+        m = int(row.max())
+        if int(row[Lq - 1]) >= gbest:
+            gi = i
+            gbest = int(row[Lq - 1])
+        if m == 0:
+            break
+        mj = int(max(j for j in range(Lq) if row[j] == m))
+        if m > best:
+            best, bi, bj = m, i, mj
+            moff = max(moff, abs(mj - i))
+    return (best, bj + 1, bi + 1, gi + 1, gbest, moff)

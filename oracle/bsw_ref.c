@@ -86,11 +86,19 @@ static int band_cap(int qlen, const bsw_ref_params* p) {
   return w;
 }
 
-int bsw_ref_extend_one(int32_t qlen, const uint8_t* q, int32_t tlen,
+/* The method with every cell value held in a lane of `bits` bits (8, 16,
+ * or 32 = plain int): Sec. 5.4.1 runs the extension in 8- or 16-bit SIMD
+ * lanes.  Such a lane holds 0 .. 2^bits - 1 and its additions saturate;
+ * the only value that can grow past what the row buffer already holds is
+ * the diagonal term d + S, so that is where the lane clamps (a negative
+ * diagonal term needs no clamp: E, F >= 0 dominate it).  With bits = 32
+ * this is the method exactly. */
+static int extend_bits(int32_t qlen, const uint8_t* q, int32_t tlen,
                        const uint8_t* t, int32_t h0, const bsw_ref_params* p,
-                       bsw_ref_result* out, bsw_ref_diag* diag) {
+                       bsw_ref_result* out, bsw_ref_diag* diag, int32_t bits) {
   int *hbuf, *ebuf; /* one row of H (shifted by one column) and of E */
   int i, j, wb, beg, end, best, bi, bj, gbest, gi, moff, rows, stop;
+  const int vmax = bits < 32 ? (1 << bits) - 1 : 0;
   int64_t cells = 0;
 
   if (h0 < 1 || h0 > BSW_REF_MAX_H0 || qlen < 0 || tlen < 0 ||
@@ -157,6 +165,7 @@ int bsw_ref_extend_one(int32_t qlen, const uint8_t* q, int32_t tlen,
       int mdiag, h;
       hbuf[j] = hl;      /* keep H(i, j-1) for row i+1 */
       mdiag = d > 0 ? d + srow[q[j]] : 0;
+      if (bits < 32 && mdiag > vmax) mdiag = vmax; /* saturating lane */
       h = imax(mdiag, imax(e, f));
       hl = h;
       if (h >= m) mj = j; /* ties: larger column (R15) */
@@ -223,6 +232,20 @@ int bsw_ref_extend_one(int32_t qlen, const uint8_t* q, int32_t tlen,
   free(hbuf);
   free(ebuf);
   return BSW_REF_OK;
+}
+
+int bsw_ref_extend_one(int32_t qlen, const uint8_t* q, int32_t tlen,
+                       const uint8_t* t, int32_t h0, const bsw_ref_params* p,
+                       bsw_ref_result* out, bsw_ref_diag* diag) {
+  return extend_bits(qlen, q, tlen, t, h0, p, out, diag, 32);
+}
+
+int bsw_ref_extend_one_bits(int32_t qlen, const uint8_t* q, int32_t tlen,
+                            const uint8_t* t, int32_t h0, const bsw_ref_params* p,
+                            bsw_ref_result* out, bsw_ref_diag* diag, int32_t bits) {
+  if (bits != 8 && bits != 16 && bits != 32) return BSW_REF_EINVAL;
+  if (bits < 32 && h0 > (1 << bits) - 1) return BSW_REF_EINVAL;
+  return extend_bits(qlen, q, tlen, t, h0, p, out, diag, bits);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -68,6 +68,13 @@ int bsw_ref_extend_one(int32_t qlen, const uint8_t* q, int32_t tlen,
                        const uint8_t* t, int32_t h0, const bsw_ref_params* p,
                        bsw_ref_result* out, bsw_ref_diag* diag);
 
+/* The same in lanes of `bits` bits (8, 16 or 32) with saturating
+ * arithmetic (Sec. 5.4.1 runs the extension in 8- or 16-bit SIMD lanes);
+ * bits = 32 is bsw_ref_extend_one.  h0 must fit the lane. */
+int bsw_ref_extend_one_bits(int32_t qlen, const uint8_t* q, int32_t tlen,
+                            const uint8_t* t, int32_t h0, const bsw_ref_params* p,
+                            bsw_ref_result* out, bsw_ref_diag* diag, int32_t bits);
+
 /* Extend n pairs.  Pair k uses q[q_off[k] .. q_off[k+1]) and
  * t[t_off[k] .. t_off[k+1]), seed score h0[k] and scoring set
  * params[param_id[k]] (param_id may be NULL: set 0 for all).  out[k] and,

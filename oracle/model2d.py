@@ -36,8 +36,10 @@ def band_cap(qlen, sc):
     return min(sc["w"], *caps)
 
 
-def extend(q, t, h0, sc):
-    """Return ((score, qle, tle, gtle, gscore, max_off), (rows, stop, cells))."""
+def extend(q, t, h0, sc, trace=None):
+    """Return ((score, qle, tle, gtle, gscore, max_off), (rows, stop, cells)).
+    With a list ``trace``, the band [beg, end) of every computed row is
+    appended to it."""
     q = np.asarray(q, dtype=np.int64)
     t = np.asarray(t, dtype=np.int64)
     Lq, Lt = len(q), len(t)
@@ -83,6 +85,8 @@ def extend(q, t, h0, sc):
         beg = max(beg, i - wb)
         end = min(end, i + wb + 1, Lq)
         BEG[i] = beg
+        if trace is not None:
+            trace.append((beg, end))
         LB[i] = max(0, h0 - oD - eD * (i + 1)) if beg == 0 else 0
         if end > beg:
             cells += end - beg
