@@ -42,7 +42,7 @@ def pack_of(cls):
     """Operations per lane-instruction that a class's arithmetic can reach:
     2 for 8- and 16-bit values (packed 16-bit instructions), 1 for 32-bit
     values."""
-    return 2 if cls.startswith(("lane8", "lane16", "wave16")) else 1
+    return 2 if cls.startswith(("lane8", "lane16")) else 1
 
 
 def host_cpu():
@@ -123,10 +123,15 @@ def kernel_symbol(cls, scorings):
         return "bsw::k_long"
     if cls == "rerun":
         return "bsw::k_wave"
-    width, cap = cls[4:].split("_q")
-    if width == "32":
+    mode, rest = cls.split("_q")
+    cap = int(rest)
+    if mode == "wave32":
+        return f"bsw::k_wavev<{max(1, (cap + 63) // 64)}>"
+    if mode == "lane32":
         return f"bsw::k_lane<2, {cap}, true>"
-    return f"bsw::k_lanec<{cap}, {sym}, {width}>"
+    if mode == "lane8":
+        return f"bsw::k_lanev<{cap}, {sym}>"
+    return f"bsw::k_lanec<{cap}, {sym}, 16>"
 
 
 def rho_key(r):

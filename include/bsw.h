@@ -163,13 +163,17 @@ int bsw_extend_batch_device(bsw_ctx* ctx, int64_t n,
 
 /* Autotuner of the batched path.  Runs the batched path over a device batch
  * (arguments as bsw_extend_batch_device; results are written to out as by
- * a normal call) once per candidate launch shape: side streams the kernel
- * classes are spread over (4, 2, 1), share of resident groups per CU for
- * the 8-bit classes (100%, 50%), and whether pairs whose score bound needs
- * 16 bits are tried at 8 bits first (yes, no).  Each candidate runs
- * eagerly: one warm-up call, then reps (1..100) timed calls; the lowest
- * median device time wins, and a shape must beat the default by more than
- * 1%.  The winner is used
+ * a normal call) under candidate launch shapes, by coordinate descent from
+ * the default shape: each knob in turn takes every value while the others
+ * stay at the best so far.  The knobs are the side streams the kernel
+ * classes are spread over (4, 2, 1), the share of resident groups per CU
+ * for the 8-bit classes (100%, 75%, 50%), whether pairs whose score bound
+ * needs 16 bits are tried at 8 bits first (yes, no), and the query cap from
+ * which the 32-bit classes run one pair per wave instead of one pair per
+ * lane (64, 128, 256, never, 32; Sec. 5.2.1 intra-task vs Sec. 5.3
+ * inter-task).  Each candidate runs eagerly: one warm-up call, then reps
+ * (1..100) timed calls, scored by their median device time; a shape must
+ * beat the best so far by more than 1%.  The winner is used
  * by every later batched call of the context with the same band limit and
  * gap symmetry, and is stored in tune_cache when one is set.  *best_ms
  * (nullable) receives its time.  Blocking. */
@@ -181,6 +185,13 @@ int bsw_ctx_tune(bsw_ctx* ctx, int64_t n, const uint8_t* q, const uint64_t* q_of
 /* The context's current launch shape: out3 = {side streams, 8-bit share of
  * resident groups in percent, 16-bit pairs tried at 8 bits (0/1)}. */
 int bsw_ctx_tune_info(bsw_ctx* ctx, int32_t out3[3]);
+
+/* The context's current launch shape for pair batches: out[0..n) receives
+ * up to four values {side streams, 8-bit share of resident groups in
+ * percent, 16-bit pairs tried at 8 bits (0/1), query cap from which 32-bit
+ * classes run in wave mode (512 = never)}.  Returns the number of values
+ * the shape has (4). */
+int bsw_ctx_shape(bsw_ctx* ctx, int32_t* out, int32_t n);
 
 /* Wait for the last asynchronous call on ctx and return its status
  * (BSW_EINVAL with the first bad pair in bsw_last_error if a pair was

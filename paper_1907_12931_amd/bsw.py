@@ -172,6 +172,8 @@ def lib():
         L.bsw_server_wait.argtypes = [_VP, ctypes.c_uint64, ctypes.c_int32]
         L.bsw_server_stats.restype = ctypes.c_int
         L.bsw_server_stats.argtypes = [_VP, ctypes.POINTER(ServerReport), ctypes.c_int32]
+        L.bsw_ctx_shape.restype = ctypes.c_int
+        L.bsw_ctx_shape.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.bsw_ctx_last_work.restype = ctypes.c_int
         L.bsw_ctx_last_work.argtypes = [_VP, _VP, ctypes.c_int32]
         L.bsw_valu_peak.restype = ctypes.c_int
@@ -392,9 +394,13 @@ class Context:
         return ms.value, self.tune_info()
 
     def tune_info(self):
-        v = (ctypes.c_int32 * 3)()
-        _check(lib().bsw_ctx_tune_info(self._h, v))
-        return {"side_streams": v[0], "occ8_pct": v[1], "spec16": v[2]}
+        """The context's launch shape for pair batches (``bsw_ctx_shape``)."""
+        v = (ctypes.c_int32 * 4)()
+        n = lib().bsw_ctx_shape(self._h, v, 4)
+        if n < 0:
+            _check(n)
+        return {"side_streams": v[0], "occ8_pct": v[1], "spec16": v[2],
+                "wave32_min_cap": v[3]}
 
     def last_kernels(self):
         """Per DP launch of the last call: list of (class name, cells, ms)."""

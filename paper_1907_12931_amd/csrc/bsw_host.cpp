@@ -53,6 +53,12 @@ void launch_wave(unsigned blocks, const PairDesc* desc, const long long* range,
                  bsw_diag* diag, uint32_t* ctr, const Status* st,
                  unsigned long long* cls_cells, hipStream_t s);
 int wave_blocks_per_cu();
+int wavev_blocks_per_cu(int cls);
+void launch_wavev(int cls, unsigned blocks, const PairDesc* desc, const long long* range,
+                  const uint8_t* q, const uint8_t* t, const KParams* kp, bsw_result* out,
+                  bsw_diag* diag, uint32_t* ctr, const Status* st,
+                  unsigned long long* cls_cells, unsigned long long* work_cells,
+                  hipStream_t s);
 void launch_long(const PairDesc* desc, const long long* range, const uint8_t* q,
                  const uint8_t* t, const KParams* kp, bsw_result* out,
                  bsw_diag* diag, uint32_t* ctr, int2* gbuf, uint8_t* gq,
@@ -218,6 +224,7 @@ struct bsw_ctx {
   long long* h_cls = nullptr;  // pinned [NCLS][2]
   int blocks_per_cu[2][NCLS] = {};
   int wave_per_cu = 1;  // resident groups per CU of the rerun kernel
+  int wavev_per_cu[NCLS] = {};  // of the wave-mode kernel of each 32-bit class
   // occupancy of the chunked classes by (symmetric variant, ring chunks)
   int occc[2][NCLS][80] = {};
   bool pending = false;
@@ -330,6 +337,26 @@ int end_launch(bsw_ctx* c, hipStream_t ls) {
   return BSW_OK;
 }
 
+// Whether a class runs in wave mode (one pair per wave) under the tuned
+// threshold: the 32-bit classes whose query cap reaches it.
+bool wave_mode(const bsw_ctx* c, int cls) {
+  static const int caps[NLW] = {LW_CAP[0], LW_CAP[1], LW_CAP[2], LW_CAP[3]};
+  return cls >= CLS_W32 && cls < CLS_LONG && caps[cls - CLS_W32] >= c->tunes[c->kind].wave32;
+}
+
+// One DP launch of a class, lane or wave mode.
+void launch_class(bsw_ctx* c, int cls, bool persist, unsigned blocks, const Work& w,
+                  const Args& a, uint32_t* qt, int ring, bool sym, hipStream_t ls) {
+  Status* st = w.st;
+  if (wave_mode(c, cls))
+    launch_wavev(cls, blocks, w.desc, w.cls_range + 2 * cls, a.q, a.t, c->d_kp, a.out, a.diag,
+                 w.ctr + cls, st, &st->cls_cells[cls], &st->work_cells[cls], ls);
+  else
+    launch_lane(cls, persist, blocks, w.desc, w.cls_range + 2 * cls, a.q, a.t, c->d_kp, a.out,
+                a.diag, w.ctr + cls, st, qt, w.ovf, &st->ovf_range[1], ring, sym,
+                &st->cls_cells[cls], &st->work_cells[cls], ls);
+}
+
 // persistent groups per CU of a class: what fits, scaled for the 8-bit
 // classes by the tuned share
 int tuned_per_cu(const bsw_ctx* c, int cls, int fit) {
@@ -359,6 +386,8 @@ BatchedPlan plan_batched(bsw_ctx* c, int wmax, bool sym) {
     } else if (cls < CLS_W32) {
       p.ring[cls] = lane8_ring_chunks(cls, wmax);
       per_cu = chunked_per_cu(c, cls, sym, p.ring[cls]);
+    } else if (wave_mode(c, cls)) {
+      per_cu = c->wavev_per_cu[cls];
     }
     p.blocks[cls] = (int64_t)tuned_per_cu(c, cls, per_cu) * c->num_cu;
     if (c->opts.max_groups > 0) p.blocks[cls] = std::min<int64_t>(p.blocks[cls], c->opts.max_groups);
@@ -399,13 +428,12 @@ int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan&
   for (int oi = 0; oi < no; ++oi) {
     const int cls = order[oi];
     hipStream_t ls = c->side[oi % nside];
-    if ((rc = begin_launch(c, cls, ls))) return rc;
-    // pairs a chunked class cannot settle in its record width go to the
+    if ((rc = begin_launch(c, cls | (wave_mode(c, cls) ? WAVE_TAG : 0), ls))) return rc;
+    // pairs a narrow class cannot settle in its record width go to the
     // rerun list
-    launch_lane(cls, true, (unsigned)p.blocks[cls], w.desc, w.cls_range + 2 * cls, a.q,
-                a.t, c->d_kp, a.out, a.diag, w.ctr + cls, st,
-                cls < CLS_W32 ? qt + p.qt_off[cls] : nullptr, w.ovf, &st->ovf_range[1],
-                p.ring[cls], sym, &st->cls_cells[cls], &st->work_cells[cls], ls);
+    launch_class(c, cls, true, (unsigned)p.blocks[cls], w, a,
+                 cls >= CLS_W16 && cls < CLS_W32 ? qt + p.qt_off[cls] : nullptr, p.ring[cls],
+                 sym, ls);
     if ((rc = end_launch(c, ls))) return rc;
   }
   for (int k = 0; k < nside; ++k) {
@@ -457,11 +485,13 @@ bool cache_lookup(const char* path, const std::string& key, Tune* t) {
     if (kv.first != key) continue;
     Tune x;
     double ms = 0;
-    if (std::sscanf(kv.second.c_str(), "{\"nside\": %d, \"occ8\": %d, \"spec16\": %d, \"ms\": %lf}",
-                    &x.nside, &x.occ8, &x.spec16, &ms) != 4)
+    if (std::sscanf(kv.second.c_str(),
+                    "{\"nside\": %d, \"occ8\": %d, \"spec16\": %d, \"wave32\": %d, "
+                    "\"ms\": %lf}",
+                    &x.nside, &x.occ8, &x.spec16, &x.wave32, &ms) != 5)
       return false;
     if (x.nside < 1 || x.nside > bsw_ctx::NSIDE || x.occ8 < 1 || x.occ8 > 100 ||
-        (x.spec16 != 0 && x.spec16 != 1))
+        (x.spec16 != 0 && x.spec16 != 1) || x.wave32 < 32 || x.wave32 > 512)
       return false;
     *t = x;
     return true;
@@ -472,8 +502,9 @@ bool cache_lookup(const char* path, const std::string& key, Tune* t) {
 int cache_store(const char* path, const std::string& key, const Tune& t, double ms) {
   auto e = cache_read(path);
   char v[160];
-  std::snprintf(v, sizeof v, "{\"nside\": %d, \"occ8\": %d, \"spec16\": %d, \"ms\": %.3f}",
-                t.nside, t.occ8, t.spec16, ms);
+  std::snprintf(v, sizeof v,
+                "{\"nside\": %d, \"occ8\": %d, \"spec16\": %d, \"wave32\": %d, \"ms\": %.3f}",
+                t.nside, t.occ8, t.spec16, t.wave32, ms);
   bool found = false;
   for (auto& kv : e)
     if (kv.first == key) {
@@ -580,34 +611,42 @@ int tune_shapes(bsw_ctx* c, int kind, int n_params, int reps, int (*run)(bsw_ctx
   scan_params(c, n_params, &wmax, &sym);
   const std::string key = tune_key(c, wmax, sym, kind);
   c->tune_keys[kind] = key;
-  // the default shape first: another shape must beat it by more than 1%
-  std::vector<Tune> cands(1);
-  for (int ns : {4, 2, 1})
-    for (int occ : {100, 50})
-      for (int sp : {1, 0}) {
-        Tune x;
-        x.nside = ns;
-        x.occ8 = occ;
-        x.spec16 = sp;
-        if (!(x == cands[0])) cands.push_back(x);
-      }
-  Tune best = c->tunes[kind];
-  double best_t = 1e300;
+  // coordinate descent from the default shape: each knob in turn takes
+  // every value with the others held at the best so far; a shape must beat
+  // the best by more than 1% (timing noise between near-equal shapes)
   std::vector<double> ts;
   int rc = BSW_OK;
-  for (const Tune& x : cands) {
+  auto score = [&](const Tune& x, double* med) {
     c->tunes[kind] = x;
     ts.clear();
     for (int r = 0; r <= reps && rc == BSW_OK; ++r) {
       rc = run(c, arg);
       if (rc == BSW_OK && r > 0) ts.push_back(c->timing[0]);
     }
-    if (rc) break;
+    if (rc) return;
     std::sort(ts.begin(), ts.end());
-    const double med = ts[ts.size() / 2];
-    if (med < best_t * (best_t < 1e300 ? 0.99 : 1.0)) {
-      best_t = med;
-      best = x;
+    *med = ts[ts.size() / 2];
+  };
+  Tune best;
+  double best_t = 1e300;
+  score(best, &best_t);
+  static const int nsides[] = {4, 2, 1}, occs[] = {100, 75, 50}, specs[] = {1, 0},
+                   waves[] = {64, 128, 256, 512, 32};
+  for (int knob = 0; knob < 4 && rc == BSW_OK; ++knob) {
+    const int* vals = knob == 0 ? nsides : knob == 1 ? occs : knob == 2 ? specs : waves;
+    const int nv = knob == 0 ? 3 : knob == 1 ? 3 : knob == 2 ? 2 : 5;
+    const Tune base = best;
+    for (int v = 0; v < nv && rc == BSW_OK; ++v) {
+      Tune x = base;
+      int& field = knob == 0 ? x.nside : knob == 1 ? x.occ8 : knob == 2 ? x.spec16 : x.wave32;
+      if (field == vals[v]) continue;
+      field = vals[v];
+      double med = 0;
+      score(x, &med);
+      if (rc == BSW_OK && med < best_t * 0.99) {
+        best_t = med;
+        best = x;
+      }
     }
   }
   c->tunes[kind] = best;
@@ -651,6 +690,9 @@ int run_plain(bsw_ctx* c, const Args& a, hipStream_t s) {
     if (count <= 0) continue;
     const int wpb = lane_waves_per_block(cls);
     blocks[cls] = ((count + 63) / 64 + wpb - 1) / wpb;
+    // wave mode: a persistent grid that takes one pair per wave at a time
+    if (wave_mode(c, cls))
+      blocks[cls] = std::min<int64_t>(count, (int64_t)c->wavev_per_cu[cls] * c->num_cu);
     if (cls < CLS_W32) (cls < CLS_W16 ? any8 : any16) = true;
     if (cls >= CLS_W16 && cls < CLS_W32) {
       ring[cls] = lane8_ring_chunks(cls, wmax);
@@ -668,11 +710,9 @@ int run_plain(bsw_ctx* c, const Args& a, hipStream_t s) {
   for (int oi = 0; oi < no; ++oi) {
     const int cls = order[oi];
     if (blocks[cls] <= 0) continue;
-    if ((rc = begin_launch(c, cls, s))) return rc;
-    launch_lane(cls, false, (unsigned)blocks[cls], w.desc, w.cls_range + 2 * cls, a.q, a.t,
-                c->d_kp, a.out, a.diag, w.ctr + cls, st, qt ? qt + qt_off[cls] : nullptr,
-                w.ovf, &st->ovf_range[1], ring[cls], sym, &st->cls_cells[cls],
-                &st->work_cells[cls], s);
+    if ((rc = begin_launch(c, cls | (wave_mode(c, cls) ? WAVE_TAG : 0), s))) return rc;
+    launch_class(c, cls, false, (unsigned)blocks[cls], w, a, qt ? qt + qt_off[cls] : nullptr,
+                 ring[cls], sym, s);
     if ((rc = end_launch(c, s))) return rc;
   }
   if (c->h_cls[2 * CLS_LONG + 1] > 0) {
@@ -734,8 +774,8 @@ void record_timing(bsw_ctx* c) {
   }
   for (int k = 0; k < c->n_launch; ++k) {
     c->lms[k] = c->graph_call ? 0.0 : elapsed(c->lev0[k], c->lev[k]);
-    c->lcells[k] = c->h_status->cls_cells[c->lcls[k]];
-    c->lwork[k] = c->h_status->work_cells[c->lcls[k]];
+    c->lcells[k] = c->h_status->cls_cells[c->lcls[k] & (WAVE_TAG - 1)];
+    c->lwork[k] = c->h_status->work_cells[c->lcls[k] & (WAVE_TAG - 1)];
   }
 }
 
@@ -934,6 +974,7 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
       c->blocks_per_cu[p][cls] = lane_blocks_per_cu(cls, p == 1, 0);
     }
   c->wave_per_cu = wave_blocks_per_cu();
+  for (int cls = CLS_W32; cls < CLS_LONG; ++cls) c->wavev_per_cu[cls] = wavev_blocks_per_cu(cls);
   (void)hipGetLastError();
   if (rc != BSW_OK) {
     bsw_ctx_destroy(c);
@@ -1049,6 +1090,14 @@ int bsw_ctx_tune_info(bsw_ctx* c, int32_t out3[3]) {
   return BSW_OK;
 }
 
+int bsw_ctx_shape(bsw_ctx* c, int32_t* out, int32_t n) {
+  if (!c || (!out && n > 0)) return fail(BSW_EINVAL, "NULL argument");
+  const Tune& t = c->tunes[KIND_PAIRS];
+  const int32_t v[4] = {t.nside, t.occ8, t.spec16, t.wave32};
+  for (int k = 0; k < n && k < 4; ++k) out[k] = v[k];
+  return 4;
+}
+
 int bsw_ctx_wait(bsw_ctx* c) {
   if (!c) return fail(BSW_EINVAL, "ctx is NULL");
   if (!c->pending) return BSW_OK;
@@ -1082,6 +1131,10 @@ const char* bsw_class_name(int32_t cls) {
       "lane8_q192", "lane8_q224", "lane8_q256", "lane16_q32", "lane16_q64",
       "lane16_q128", "lane16_q256", "lane32_q32", "lane32_q64", "lane32_q128",
       "lane32_q256", "long", "rerun"};
+  static const char* wave_names[NLW] = {"wave32_q32", "wave32_q64", "wave32_q128",
+                                        "wave32_q256"};
+  if (cls >= CLS_W32 + WAVE_TAG && cls < CLS_LONG + WAVE_TAG)
+    return wave_names[cls - WAVE_TAG - CLS_W32];
   return cls >= 0 && cls <= NCLS ? names[cls] : "?";
 }
 

@@ -82,6 +82,10 @@ struct ReqSlice {
   const uint8_t* pid;        // its n scoring-set indices (device) or null
 };
 
+// Launch records name a wave-mode launch of a 32-bit class as the class
+// plus WAVE_TAG (its cells are counted under the class).
+constexpr int WAVE_TAG = 32;
+
 constexpr int LONG_SLOTS = 256;          // waves running the long class
 constexpr int LONG_SLOT_COLS = 65536;    // row-buffer entries per slot
 

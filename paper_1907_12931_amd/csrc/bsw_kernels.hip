@@ -1674,6 +1674,191 @@ k_wave(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
   if (lane == 0 && acc) atomicAdd(cls_cells, acc);
 }
 
+// ---------------------------------------------------------------------------
+// Wave mode with the row in registers (32-bit values, queries up to
+// 64 * NSEG).  The intra-task form of Sec. 5.2.1 for pairs whose values or
+// bands are wide: one pair per wave, lane l holding columns l, l + 64, ...
+// of the row buffer (H shifted by one column, and E) in registers, so a
+// row is NSEG wave steps of 64 columns.  Only F runs along the row; within
+// a step it is a max-plus prefix over the lanes (a DPP scan),
+//   F(jb + l) = max(0, F(jb) - l e, max_{l' < l} (M(jb + l') - o - e + l' e)
+//                   - (l - 1) e)      (insertion costs o, e),
+// and the step's last F and H carry into the next step.  All per-pair state
+// is wave-uniform.  The right-edge column 64 * NSEG (only reached when the
+// query fills the class) is a wave-uniform scalar: it is never inside a
+// band, so only its H (the query-end score) is ever read.
+
+__device__ __forceinline__ int wave_max_i(int v) { return wave_max(v); }
+
+template <int NSEG>
+__global__ void __launch_bounds__(64)
+k_wavev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
+        const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
+        const KParams* __restrict__ kp, bsw_result* __restrict__ out,
+        bsw_diag* __restrict__ diag, uint32_t* ctr, const Status* st,
+        unsigned long long* __restrict__ cls_cells,
+        unsigned long long* __restrict__ work_cells) {
+  if (st->bad) return;
+  constexpr int CAPW = 64 * NSEG;
+  const int lane = threadIdx.x;
+  const long long begin = range[0], count = range[1];
+  unsigned long long acc = 0, span = 0;
+  for (;;) {
+    uint32_t v0 = 0;
+    if (lane == 0) v0 = atomicAdd(ctr, 1u);
+    const uint32_t k = wave_first(__shfl(v0, 0));
+    if (k >= count) break;
+    const PairDesc pd = desc[begin + k];
+    const KParams& P = kp[pd.pid];
+    const int Lq = pd.ql, Lt = pd.tl, h0 = pd.h0;
+    const int oD = P.o_del, eD = P.e_del, oI = P.o_ins, eI = P.e_ins;
+    const int oeD = P.oe_del, oeI = P.oe_ins, zd = P.zdrop;
+    const int wb = band_cap(P, Lq);
+    const uint8_t* qs = q + pd.qo;
+    const uint8_t* ts = t + pd.to;
+    // row buffer: first row of Eq. (3), E = 0; query codes
+    int hd[NSEG], ev[NSEG];
+    uint32_t qc[NSEG];
+#pragma unroll
+    for (int sg = 0; sg < NSEG; ++sg) {
+      const int j = lane + 64 * sg;
+      hd[sg] = j == 0 ? h0 : (j <= Lq ? imax(0, h0 - oI - eI * j) : 0);
+      ev[sg] = 0;
+      qc[sg] = j < Lq ? qs[j] : 0u;
+    }
+    int hcap = Lq == CAPW ? imax(0, h0 - oI - eI * CAPW) : 0;  // column CAPW
+    int best = h0, bi = -1, bj = -1, gbest = -1, gi = -1, moff = 0;
+    int beg = 0, end = Lq, rows = 0, stop = 0;
+    long long cells = 0;
+    uint32_t tnext = Lt > 0 ? ts[0] : 0u;
+    for (int i = 0; i < Lt; ++i) {
+      ++rows;
+      const uint32_t tb = tnext;
+      if (i + 1 < Lt) tnext = ts[i + 1];
+      beg = imax(beg, i - wb);
+      end = imin(imin(end, i + wb + 1), Lq);
+      if (end > beg) cells += end - beg;
+      const uint32_t lo = P.prow[tb][0], hi = P.prow[tb][1];
+      const int hl = beg == 0 ? imax(0, h0 - oD - eD * (i + 1)) : 0;  // H(i, beg - 1)
+      int hin = hl;   // H(i, jb - 1) entering a step
+      int fin = 0;    // F(i, jb) entering a step
+      int lh = -1, lj = -1;  // this lane's row maximum and its column
+      // steps holding the band and its right-edge column (just the right
+      // edge when the band is empty)
+      const int s0 = imin(beg, end) >> 6, s1 = end >> 6;
+      span += (unsigned)(imin(s1, NSEG - 1) + 1 - imin(s0, NSEG));
+#pragma unroll
+      for (int sg = 0; sg < NSEG; ++sg) {
+        if (sg < s0 || sg > s1) continue;
+        const int jb = 64 * sg, j = jb + lane;
+        const bool in = j >= beg && j < end;
+        const int d = hd[sg], e = ev[sg];
+        const int sc = score_of(lo, hi, qc[sg]);
+        const int M = d > 0 ? d + sc : 0;
+        const int X = wave_prefix_max_excl(in ? M - oeI + lane * eI : NEG);
+        const int F = imax(imax(fin - lane * eI, X - (lane - 1) * eI), 0);
+        const int h = imax(imax(M, e), F);
+        const int Fn = imax(imax(F - eI, M - oeI), 0);
+        // H(i, j - 1) for this lane's column: the lane below, or the value
+        // carried in from the previous step
+        int hp = __builtin_amdgcn_update_dpp(0, h, 0x138, 0xf, 0xf, false);  // wave_shr:1
+        hp = lane == 0 ? hin : hp;
+        // the band's first column and the right edge of an empty band take
+        // the row's left boundary H(i, beg - 1)
+        if (j == (beg < end ? beg : end)) hp = hl;
+        if (in || j == end) {
+          hd[sg] = hp;
+          ev[sg] = in ? imax(imax(e - eD, M - oeD), 0) : 0;
+        }
+        if (in && h >= lh) {
+          lh = h;
+          lj = j;
+        }
+        hin = __builtin_amdgcn_readlane(h, 63);
+        fin = __builtin_amdgcn_readlane(Fn, 63);
+      }
+      // right edge in the scalar column CAPW (R8)
+      if (end == CAPW) hcap = hin;
+      // row maximum, ties to the larger column (R15)
+      const int m = imax(wave_max_i(lh), 0);
+      const int mj = wave_max_i(lh == m && m > 0 ? lj : -1);
+      // best score touching the end of the query (Sec. 5.4 (b)): the stored
+      // H(i, end - 1) at column end
+      if (imax(beg, end) == Lq) {
+        int hend;
+        if (end == CAPW) {
+          hend = hcap;
+        } else {
+          hend = 0;
+#pragma unroll
+          for (int sg = 0; sg < NSEG; ++sg)
+            if ((end >> 6) == sg) hend = __builtin_amdgcn_readlane(hd[sg], end & 63);
+        }
+        gi = hend >= gbest ? i : gi;
+        gbest = imax(gbest, hend);
+      }
+      if (m == 0) {
+        stop = 1;
+        break;
+      }
+      if (m > best) {
+        best = m;
+        bi = i;
+        bj = mj;
+        moff = imax(moff, mj > i ? mj - i : i - mj);
+      } else if (zd > 0) {
+        const int drift = (i - bi) - (mj - bj);
+        const int drop = best - m - (drift > 0 ? drift * eD : -drift * eI);
+        if (drop > zd) {
+          stop = 2;
+          break;
+        }
+      }
+      // shrink the band by its empty ends (Sec. 5.1 (c)): the first
+      // non-empty index in [beg, end), the last one in [beg, end]
+      int nb = end;
+#pragma unroll
+      for (int sg = 0; sg < NSEG; ++sg) {
+        const int j = lane + 64 * sg;
+        const unsigned long long mk =
+            __ballot(j >= beg && j < end && (hd[sg] | ev[sg]) != 0);
+        if (nb == end && mk) nb = 64 * sg + __builtin_ctzll(mk);
+      }
+      int x = nb - 1;
+      if (end == CAPW && hcap != 0) x = CAPW;
+#pragma unroll
+      for (int sg = 0; sg < NSEG; ++sg) {
+        const int j = lane + 64 * sg;
+        const unsigned long long mk =
+            __ballot(j >= nb && j <= end && (hd[sg] | ev[sg]) != 0);
+        if (mk) x = imax(x, 64 * sg + 63 - __builtin_clzll(mk));
+      }
+      beg = nb;
+      end = imin(x + 2, Lq);
+    }
+    if (lane == 0) {
+      bsw_result res;
+      res.score = best;
+      res.qle = bj + 1;
+      res.tle = bi + 1;
+      res.gtle = gi + 1;
+      res.gscore = gbest;
+      res.max_off = moff;
+      out[pd.idx] = res;
+      if (diag) {
+        bsw_diag dg;
+        dg.rows = rows;
+        dg.stop = stop;
+        dg.cells = cells;
+        diag[pd.idx] = dg;
+      }
+    }
+    acc += (unsigned long long)cells;
+  }
+  if (lane == 0 && acc) atomicAdd(cls_cells, acc);
+  if (lane == 0 && span) atomicAdd(work_cells, span * 64ull);
+}
+
 // Queries longer than 256: one pair per wave, lane 0 runs it with a
 // 32-bit row buffer in HBM (slot per wave); waves pull pairs from a counter.
 __global__ void __launch_bounds__(64)
@@ -1901,6 +2086,34 @@ void launch_wave(unsigned blocks, const PairDesc* desc, const long long* range,
                  unsigned long long* cls_cells, hipStream_t s) {
   hipLaunchKernelGGL(k_wave, dim3(blocks), dim3(64), 0, s, desc, range, q, t, kp, out, diag,
                      ctr, st, cls_cells);
+}
+
+typedef void (*WaveVFn)(const PairDesc*, const long long*, const uint8_t*, const uint8_t*,
+                        const KParams*, bsw_result*, bsw_diag*, uint32_t*, const Status*,
+                        unsigned long long*, unsigned long long*);
+
+// wave-mode kernel of a 32-bit class: steps of 64 columns covering its cap
+static WaveVFn wavev_fn(int cls) {
+  const int cap = cls_cap(cls);
+  if (cap <= 64) return k_wavev<1>;
+  if (cap <= 128) return k_wavev<2>;
+  return k_wavev<4>;
+}
+
+int wavev_blocks_per_cu(int cls) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, wavev_fn(cls), 64, 0) != hipSuccess)
+    return 1;
+  return nb < 1 ? 1 : nb;
+}
+
+void launch_wavev(int cls, unsigned blocks, const PairDesc* desc, const long long* range,
+                  const uint8_t* q, const uint8_t* t, const KParams* kp, bsw_result* out,
+                  bsw_diag* diag, uint32_t* ctr, const Status* st,
+                  unsigned long long* cls_cells, unsigned long long* work_cells,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(wavev_fn(cls), dim3(blocks), dim3(64), 0, s, desc, range, q, t, kp, out,
+                     diag, ctr, st, cls_cells, work_cells);
 }
 
 int wave_blocks_per_cu() {
