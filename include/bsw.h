@@ -161,6 +161,33 @@ int bsw_extend_batch_device(bsw_ctx* ctx, int64_t n,
                             bsw_result* out, bsw_diag* diag,
                             void* stream, int32_t async);
 
+/* Allocation-free form of bsw_extend_batch_device, for callers that cannot
+ * allocate device memory: code being captured into a HIP graph, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, checks,
+ * results and status as bsw_extend_batch_device on the batched path, but
+ * the call allocates nothing (no hipMalloc/hipFree, no library routine that
+ * allocates) and captures no graph of its own: its workspace lives in one
+ * fixed 16 MiB device array per GPU, reserved with the library and held
+ * until the process ends, whose address each context takes when it is
+ * created.  Limits: at most BSW_NOALLOC_MAX_PAIRS pairs per call (more
+ * gives BSW_ETOOBIG before anything is enqueued); pairs whose values need
+ * 16-bit records run on at most 64 workgroups per class and queries longer
+ * than 256 on 4 waves, so such batches are slower than on the ordinary
+ * entry point; the context's path must be BSW_PATH_BATCHED (else
+ * BSW_EINVAL).  Every context on a GPU shares that GPU's array, and it
+ * keeps the last call's contents (each call clears what must start at
+ * zero), so calls that overlap on one GPU, from any context or stream,
+ * race and must be serialised by the caller.  async as in
+ * bsw_extend_batch_device (under graph capture pass async != 0). */
+#define BSW_NOALLOC_MAX_PAIRS 131072
+int bsw_extend_batch_device_noalloc(bsw_ctx* ctx, int64_t n,
+                                    const uint8_t* q, const uint64_t* q_off,
+                                    const uint8_t* t, const uint64_t* t_off,
+                                    const int32_t* h0, const uint8_t* param_id,
+                                    const bsw_params* params, int32_t n_params,
+                                    bsw_result* out, bsw_diag* diag,
+                                    void* stream, int32_t async);
+
 /* Autotuner of the batched path.  Runs the batched path over a device batch
  * (arguments as bsw_extend_batch_device; results are written to out as by
  * a normal call) under candidate launch shapes, by coordinate descent from

@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbsw.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ETOOBIG, EBUSY, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_MAX_PAIRS = 131072
 PATH_BATCHED, PATH_PLAIN = 0, 1
 STATUS_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
                 ETOOBIG: "ETOOBIG", EBUSY: "EBUSY", ETIMEOUT: "ETIMEOUT"}
@@ -172,6 +173,10 @@ def lib():
         L.bsw_server_wait.argtypes = [_VP, ctypes.c_uint64, ctypes.c_int32]
         L.bsw_server_stats.restype = ctypes.c_int
         L.bsw_server_stats.argtypes = [_VP, ctypes.POINTER(ServerReport), ctypes.c_int32]
+        L.bsw_extend_batch_device_noalloc.restype = ctypes.c_int
+        L.bsw_extend_batch_device_noalloc.argtypes = [
+            _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP,
+            ctypes.POINTER(Params), ctypes.c_int32, _VP, _VP, _VP, ctypes.c_int32]
         L.bsw_ctx_shape.restype = ctypes.c_int
         L.bsw_ctx_shape.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.bsw_ctx_last_work.restype = ctypes.c_int
@@ -278,6 +283,21 @@ class Context:
         pid = dev.get("param_id")
         s = stream.cuda_stream if stream is not None else None
         _check(lib().bsw_extend_batch_device(
+            self._h, n, dev["q"].data_ptr(), dev["q_off"].data_ptr(),
+            dev["t"].data_ptr(), dev["t_off"].data_ptr(), dev["h0"].data_ptr(),
+            pid.data_ptr() if pid is not None else None, params, len(params),
+            out.data_ptr(), diag.data_ptr() if diag is not None else None, s,
+            1 if async_ else 0))
+
+    def extend_device_noalloc(self, dev, scorings, out, diag=None, stream=None,
+                              async_=False):
+        """As ``extend_device``, through the allocation-free entry point
+        (``bsw_extend_batch_device_noalloc``)."""
+        n = dev["h0"].numel()
+        params = make_params(scorings)
+        pid = dev.get("param_id")
+        s = stream.cuda_stream if stream is not None else None
+        _check(lib().bsw_extend_batch_device_noalloc(
             self._h, n, dev["q"].data_ptr(), dev["q_off"].data_ptr(),
             dev["t"].data_ptr(), dev["t_off"].data_ptr(), dev["h0"].data_ptr(),
             pid.data_ptr() if pid is not None else None, params, len(params),

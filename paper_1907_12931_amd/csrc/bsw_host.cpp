@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <string>
@@ -59,7 +60,7 @@ void launch_wavev(int cls, unsigned blocks, const PairDesc* desc, const long lon
                   bsw_diag* diag, uint32_t* ctr, const Status* st,
                   unsigned long long* cls_cells, unsigned long long* work_cells,
                   hipStream_t s);
-void launch_long(const PairDesc* desc, const long long* range, const uint8_t* q,
+void launch_long(int slots, const PairDesc* desc, const long long* range, const uint8_t* q,
                  const uint8_t* t, const KParams* kp, bsw_result* out,
                  bsw_diag* diag, uint32_t* ctr, int2* gbuf, uint8_t* gq,
                  const Status* st, unsigned long long* cls_cells, hipStream_t s);
@@ -227,6 +228,8 @@ struct bsw_ctx {
   int wavev_per_cu[NCLS] = {};  // of the wave-mode kernel of each 32-bit class
   // occupancy of the chunked classes by (symmetric variant, ring chunks)
   int occc[2][NCLS][80] = {};
+  bool noalloc = false;     // the call being enqueued uses the scratch
+  void* scratch = nullptr;  // device address of this device's scratch array
   bool pending = false;
   hipStream_t pending_stream = nullptr;
   int (*pending_done)(bsw_ctx*) = nullptr;  // completion check of that call
@@ -374,7 +377,47 @@ struct BatchedPlan {
   int ring[NCLS + 1] = {};
   size_t qt_off[NCLS + 1] = {};
   size_t qt_words = 0;
+  // device buffers of the call: query tiles of the 16-bit classes and the
+  // row-buffer slots of the long class
+  uint32_t* qt = nullptr;
+  int2* gbuf = nullptr;
+  uint8_t* gq = nullptr;
+  int long_slots = LONG_SLOTS;
 };
+
+// The fixed-size device scratch of the allocation-free entry point: one
+// array per device, the same for every context on it (its address is taken
+// once per device, with that device current).  It holds a call's
+// workspace for up to BSW_NOALLOC_MAX_PAIRS pairs, the query tiles of the
+// 16-bit classes with their grids capped at NOALLOC_GROUPS groups, and
+// NOALLOC_LONG_SLOTS row-buffer slots for queries longer than 256.
+constexpr int NOALLOC_GROUPS = 64;
+constexpr int NOALLOC_LONG_SLOTS = 4;
+constexpr size_t NOALLOC_BYTES = (size_t)16 << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[128] = {};
+
+// Device address of the scratch array on the current device `dev`.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= 128) return fail(BSW_EDEVICE, "device %d: no scratch slot", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(BSW_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BSW_OK;
+}
 
 BatchedPlan plan_batched(bsw_ctx* c, int wmax, bool sym) {
   BatchedPlan p;
@@ -391,6 +434,8 @@ BatchedPlan plan_batched(bsw_ctx* c, int wmax, bool sym) {
     }
     p.blocks[cls] = (int64_t)tuned_per_cu(c, cls, per_cu) * c->num_cu;
     if (c->opts.max_groups > 0) p.blocks[cls] = std::min<int64_t>(p.blocks[cls], c->opts.max_groups);
+    if (c->noalloc && cls >= CLS_W16 && cls < CLS_W32)
+      p.blocks[cls] = std::min<int64_t>(p.blocks[cls], NOALLOC_GROUPS);
     if (cls >= CLS_W16 && cls < CLS_W32) {
       p.qt_off[cls] = p.qt_words;
       p.qt_words += (size_t)p.blocks[cls] * lane8_qtile_words(cls);
@@ -408,9 +453,9 @@ BatchedPlan plan_batched(bsw_ctx* c, int wmax, bool sym) {
 int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan& p,
                     bool sym, hipStream_t s) {
   int rc;
-  uint32_t* qt = (uint32_t*)c->qtiles.p;
-  int2* gbuf = (int2*)c->longbuf.p;
-  uint8_t* gq = (uint8_t*)(gbuf + (size_t)LONG_SLOTS * LONG_SLOT_COLS);
+  uint32_t* qt = p.qt;
+  int2* gbuf = p.gbuf;
+  uint8_t* gq = p.gq;
   Status* st = w.st;
   const bool ev = !c->graph_call;
   if (ev) HIPCHK(hipEventRecord(c->ev[0], s));
@@ -441,8 +486,8 @@ int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan&
     HIPCHK(hipStreamWaitEvent(s, c->join_ev[k], 0));
   }
   if ((rc = begin_launch(c, CLS_LONG, s))) return rc;
-  launch_long(w.desc, w.cls_range + 2 * CLS_LONG, a.q, a.t, c->d_kp, a.out, a.diag,
-              w.ctr + CLS_LONG, gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
+  launch_long(p.long_slots, w.desc, w.cls_range + 2 * CLS_LONG, a.q, a.t, c->d_kp, a.out,
+              a.diag, w.ctr + CLS_LONG, gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
   if ((rc = end_launch(c, s))) return rc;
   // the rerun, one pair per wave with 32-bit values
   if ((rc = begin_launch(c, NCLS, s))) return rc;
@@ -544,14 +589,38 @@ int run_batched(bsw_ctx* c, const Args& a, hipStream_t s) {
   int wmax;
   bool sym;
   scan_params(c, a.n_params, &wmax, &sym);
-  pick_tune(c, wmax, sym);
   const Layout L = layout_for(a.n);
   int rc;
+  if (c->noalloc) {
+    // everything in the device scratch, no graph of our own, no cache read
+    BatchedPlan p = plan_batched(c, wmax, sym);
+    char* base = (char*)c->scratch;
+    const size_t qt_at = align_up(L.total, 256);
+    const size_t lb_at = align_up(qt_at + p.qt_words * 4, 256);
+    const size_t lb_bytes = (size_t)NOALLOC_LONG_SLOTS * LONG_SLOT_COLS * (sizeof(int2) + 1);
+    if (lb_at + lb_bytes > NOALLOC_BYTES)
+      return fail(BSW_ETOOBIG, "%lld pairs need more than the %zu-byte scratch", (long long)a.n,
+                  NOALLOC_BYTES);
+    p.qt = (uint32_t*)(base + qt_at);
+    p.gbuf = (int2*)(base + lb_at);
+    p.gq = (uint8_t*)(p.gbuf + (size_t)NOALLOC_LONG_SLOTS * LONG_SLOT_COLS);
+    p.long_slots = NOALLOC_LONG_SLOTS;
+    const Work w = carve(base, L);
+    c->last_st = w.st;
+    HIPCHK(hipMemcpyAsync(c->d_kp, c->h_kp, sizeof(KParams) * a.n_params,
+                          hipMemcpyHostToDevice, s));
+    c->graph_call = false;
+    return enqueue_batched(c, a, w, p, sym, s);
+  }
+  pick_tune(c, wmax, sym);
   if ((rc = c->ws.ensure(L.total))) return rc;
-  const BatchedPlan p = plan_batched(c, wmax, sym);
+  BatchedPlan p = plan_batched(c, wmax, sym);
   if ((rc = c->qtiles.ensure(p.qt_words * 4))) return rc;
   if ((rc = c->longbuf.ensure((size_t)LONG_SLOTS * LONG_SLOT_COLS * (sizeof(int2) + 1))))
     return rc;
+  p.qt = (uint32_t*)c->qtiles.p;
+  p.gbuf = (int2*)c->longbuf.p;
+  p.gq = (uint8_t*)(p.gbuf + (size_t)LONG_SLOTS * LONG_SLOT_COLS);
   const Work w = carve((char*)c->ws.p, L);
   c->last_st = w.st;
   HIPCHK(hipMemcpyAsync(c->d_kp, c->h_kp, sizeof(KParams) * a.n_params,
@@ -721,8 +790,8 @@ int run_plain(bsw_ctx* c, const Args& a, hipStream_t s) {
     int2* gbuf = (int2*)c->longbuf.p;
     uint8_t* gq = (uint8_t*)(gbuf + (size_t)LONG_SLOTS * LONG_SLOT_COLS);
     if ((rc = begin_launch(c, CLS_LONG, s))) return rc;
-    launch_long(w.desc, w.cls_range + 2 * CLS_LONG, a.q, a.t, c->d_kp, a.out, a.diag,
-                w.ctr + CLS_LONG, gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
+    launch_long(LONG_SLOTS, w.desc, w.cls_range + 2 * CLS_LONG, a.q, a.t, c->d_kp, a.out,
+                a.diag, w.ctr + CLS_LONG, gbuf, gq, st, &st->cls_cells[CLS_LONG], s);
     if ((rc = end_launch(c, s))) return rc;
   }
   // the rerun: its count is only known on the device, so the grid is
@@ -974,6 +1043,10 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
       c->blocks_per_cu[p][cls] = lane_blocks_per_cu(cls, p == 1, 0);
     }
   c->wave_per_cu = wave_blocks_per_cu();
+  if (rc == BSW_OK) {
+    const int rs = scratch_address(c->device, &c->scratch);
+    if (rs != BSW_OK) rc = rs;
+  }
   for (int cls = CLS_W32; cls < CLS_LONG; ++cls) c->wavev_per_cu[cls] = wavev_blocks_per_cu(cls);
   (void)hipGetLastError();
   if (rc != BSW_OK) {
@@ -1040,6 +1113,42 @@ int bsw_extend_batch_device(bsw_ctx* c, int64_t n, const uint8_t* q,
   const Args a = {n, q, q_off, t, t_off, h0, param_id, n_params, out, diag,
                  nullptr, nullptr, false};
   rc = run_pipeline(c, a, s);
+  if (rc) return rc;
+  if (async) {
+    ctx_set_pending(c, s, finish_call);
+    return BSW_OK;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return finish_call(c);
+}
+
+int bsw_extend_batch_device_noalloc(bsw_ctx* c, int64_t n, const uint8_t* q,
+                                    const uint64_t* q_off, const uint8_t* t,
+                                    const uint64_t* t_off, const int32_t* h0,
+                                    const uint8_t* param_id, const bsw_params* params,
+                                    int32_t n_params, bsw_result* out, bsw_diag* diag,
+                                    void* stream, int32_t async) {
+  if (!c) return fail(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
+  if (n < 0) return fail(BSW_EINVAL, "n = %lld out of range", (long long)n);
+  if (n > BSW_NOALLOC_MAX_PAIRS)
+    return fail(BSW_ETOOBIG, "n = %lld exceeds the allocation-free limit of %d pairs",
+                (long long)n, BSW_NOALLOC_MAX_PAIRS);
+  if (n == 0) return BSW_OK;
+  int rc = check_params(params, n_params);
+  if (rc) return rc;
+  if (!q_off || !t_off || !h0 || !out)
+    return fail(BSW_EINVAL, "a required device pointer is NULL");
+  if (c->opts.path != BSW_PATH_BATCHED)
+    return fail(BSW_EINVAL, "the allocation-free entry runs the batched path");
+  if ((rc = set_device(c))) return rc;
+  for (int i = 0; i < n_params; ++i) c->h_kp[i] = to_kparams(params[i]);
+  hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+  const Args a = {n, q, q_off, t, t_off, h0, param_id, n_params, out, diag,
+                 nullptr, nullptr, false};
+  c->noalloc = true;
+  rc = run_pipeline(c, a, s);
+  c->noalloc = false;
   if (rc) return rc;
   if (async) {
     ctx_set_pending(c, s, finish_call);

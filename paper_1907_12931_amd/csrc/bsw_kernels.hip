@@ -2122,11 +2122,12 @@ int wave_blocks_per_cu() {
   return nb < 1 ? 1 : nb;
 }
 
-void launch_long(const PairDesc* desc, const long long* range, const uint8_t* q,
+// slots waves, wave w using row-buffer slot w of gbuf / gq
+void launch_long(int slots, const PairDesc* desc, const long long* range, const uint8_t* q,
                  const uint8_t* t, const KParams* kp, bsw_result* out,
                  bsw_diag* diag, uint32_t* ctr, int2* gbuf, uint8_t* gq,
                  const Status* st, unsigned long long* cls_cells, hipStream_t s) {
-  hipLaunchKernelGGL(k_long, dim3(LONG_SLOTS), dim3(64), 0, s, desc, range, q, t,
+  hipLaunchKernelGGL(k_long, dim3(slots), dim3(64), 0, s, desc, range, q, t,
                      kp, out, diag, ctr, gbuf, gq, st, cls_cells);
 }
 
