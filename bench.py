@@ -139,19 +139,20 @@ def rho_key(r):
 
 
 def serve(bsw, synth, batch, host, capacity, rho, n_requests, seed=3):
-    """Open-loop serving run: request sizes log-uniform in [1e3, 1e5] pairs,
-    each a contiguous slice of the batch's host arrays (in pinned memory),
-    arriving as a Poisson process at rho x the batched path's capacity
-    (pairs/s).
-    Latency = submit -> results in the caller's buffers."""
+    """Serving run: request sizes log-uniform in [1e3, 1e5] pairs, each a
+    contiguous slice of the batch's host arrays (in pinned memory), arriving
+    as a Poisson process at rho x capacity (pairs/s); rho = None submits
+    them all at once (closed loop: the server's sustained capacity, host
+    transfers included).  Latency = submit -> results in the caller's
+    buffers."""
     import threading
     import numpy as np
     sizes = synth.serving_requests(n_requests=n_requests, seed=seed)
     rng = np.random.default_rng(seed)
     n = len(batch["h0"])
     starts = rng.integers(0, n - sizes + 1)
-    gaps = rng.exponential(sizes / (rho * capacity))
-    arrivals = np.cumsum(gaps)
+    arrivals = (np.cumsum(rng.exponential(sizes / (rho * capacity))) if rho
+                else np.zeros(n_requests))
     reqs = [{"q": host["q"], "t": host["t"],
              "q_off": host["q_off"][a:a + m + 1], "t_off": host["t_off"][a:a + m + 1],
              "h0": host["h0"][a:a + m], "scorings": batch["scorings"]}
@@ -174,7 +175,9 @@ def serve(bsw, synth, batch, host, capacity, rho, n_requests, seed=3):
             ready.release()
         th.join()
         st = srv.stats()
-    return {"offered_pairs_per_s": round(rho * capacity), "requests": n_requests,
+    return {"offered_pairs_per_s": round(rho * capacity) if rho else None,
+            "delivered_pairs_per_s": round(st["pairs"] / st["window_s"]) if st["window_s"] else None,
+            "requests": n_requests,
             "pairs": st["pairs"], "batches": st["batches"],
             "mean_batch_pairs": round(st["mean_batch_pairs"]),
             "p50_ms": round(st["lat_p50_ms"], 3), "p99_ms": round(st["lat_p99_ms"], 3),
@@ -200,25 +203,39 @@ def seed_driver(bsw, synth, torch, np, tune_cache, steps, warmup, tune=True):
         ms, tuned = ctx.tune_seeds(dev, sw["scoring"], out, reps=3)
         tuned["tune_best_ms"] = round(ms, 3)
         log(f"seed driver tuned: {tuned}")
+    keep = torch.empty(max(ns, 1), dtype=torch.uint8, device="cuda")
     for _ in range(max(1, warmup)):
         ctx.extend_seeds_device(dev, sw["scoring"], out)
+        ctx.filter_seeds_device(dev["seeds"], out, keep)
     cells = ctx.last_cells()
     torch.cuda.synchronize()
     tms = []
     t = time.perf_counter()
+    # a step extends every seed, then drops the ones an earlier alignment of
+    # the same chain covers (Sec. 5.3.2)
     for _ in range(steps):
         ctx.extend_seeds_device(dev, sw["scoring"], out)
         tms.append(ctx.last_timing())
+        ctx.filter_seeds_device(dev["seeds"], out, keep)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t) / steps
     assert ctx.last_cells() == cells
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        ctx.filter_seeds_device(dev["seeds"], out, keep, stream=torch.cuda.current_stream())
+    e1.record()
+    torch.cuda.synchronize()
+    filter_ms = e0.elapsed_time(e1) / 5
+    kept = int(keep[:ns].sum().item())
     ctx.close()
     tm = np.mean(np.asarray(tms), axis=0)
     leg = {"value": round(ns / wall, 1), "unit": "seeds/s",
            "reads_per_s": round(nr / wall, 1), "gcups": round(cells / wall / 1e9, 2),
            "ms_per_step": round(wall * 1e3, 3), "device_ms": round(float(tm[0]), 3),
            "left_ms": round(float(tm[1]), 3), "right_ms": round(float(tm[2]), 3),
-           "dp_launches": int(tm[3]),
+           "dp_launches": int(tm[3]), "filter_ms": round(filter_ms, 3),
+           "kept": kept,
            "workload": f"{nr} reads x {synth.SEED_BENCH.get('read_len', 151)} bp from a "
                        f"{len(sw['ref'])}-base random reference, 1-5% substitutions, "
                        f"0.1-1% indels, 1% N; {ns} seeds (exact runs >= 19 bp, <= 3 per "
@@ -494,6 +511,9 @@ def main():
     ap.add_argument("--plain-only", action="store_true",
                     help="run only the plain path of the main workload (no tuner) and "
                          "print its timings (for counter profiles of the DP kernels)")
+    ap.add_argument("--workload", default="batched_mix",
+                    choices=("batched_mix", "read_scale", "wide_band"),
+                    help="with --plain-only: the workload to run (default: the main one)")
     ap.add_argument("--peak-only", action="store_true",
                     help="print the measured integer-VALU peaks and exit")
     ap.add_argument("--no-tune", action="store_true",
@@ -562,8 +582,12 @@ def main():
     tune_cache = os.path.join(tempfile.mkdtemp(prefix="bsw_tune_"), "tune.json")
     if args.plain_only:
         # one path alone (for counter profiles of the DP kernels)
+        if args.workload != "batched_mix":
+            batch = {"read_scale": synth.read_scale,
+                     "wide_band": synth.wide_band}[args.workload](workers=workers)
         leg = bsw_paths(bsw, torch, np, batch, args.steps, args.warmup, tune_cache,
-                        tune=False, batched=False)
+                        tune=False, batched=False,
+                        min_lane_bits=32 if args.workload == "wide_band" else 0)
         print(json.dumps(strip(leg["plain"])), flush=True)
         return
     peaks = valu_peaks(bsw)
@@ -594,12 +618,21 @@ def main():
 
     serving = None
     if not args.no_serve:
-        capacity = n / (b["ms_per_step"] / 1e3)  # pairs/s of the batched path
+        resident = n / (b["ms_per_step"] / 1e3)  # pairs/s of the batched path
         # request data in pinned host memory, as a serving front end keeps it
         host = {k: pinned(batch[k]) for k in ("q", "t", "q_off", "t_off", "h0")}
-        serving = {rho_key(r): serve(bsw, synth, batch, host, capacity, r,
-                                     args.serve_requests)
-                   for r in (0.5, 0.8)}
+        # the server's own sustained rate (uploads and result copies
+        # included): every request submitted at once
+        closed = serve(bsw, synth, batch, host, resident, None, args.serve_requests)
+        capacity = closed["delivered_pairs_per_s"]
+        serving = {"resident_pairs_per_s": round(resident), "capacity": closed}
+        serving.update({rho_key(r): serve(bsw, synth, batch, host, capacity, r,
+                                          args.serve_requests)
+                        for r in (0.5, 0.8)})
+        # beside them, the same loads relative to the resident-data rate
+        serving.update({"resident_" + rho_key(r): serve(bsw, synth, batch, host, resident, r,
+                                                        args.serve_requests)
+                        for r in (0.5, 0.8)})
         log(f"serving: {serving}")
 
     sal_leg = sal_w = None

@@ -416,6 +416,21 @@ int bsw_extend_seeds_device(bsw_ctx* ctx, const uint8_t* reads, uint64_t reads_l
                             const bsw_seed* seeds, int64_t n, const bsw_params* params,
                             bsw_seed_result* out, void* stream, int32_t async);
 
+/* The filter after extending every seed (Sec. 5.3.2 extends all seeds of a
+ * read first, removing the dependence between them, then drops the ones
+ * the sequential mapper would not have extended).  A chain is a run of
+ * consecutive seeds with the same read, in the order given (the mapper's
+ * order, best seed first).  Walking a chain, a seed is dropped when the
+ * extension of an earlier kept seed of the chain contains it both in the
+ * read ([qbeg, qend) holds [qb, qe)) and in the reference ([rbeg, rend)
+ * holds [rb, rb + qe - qb)); the first seed of a chain is kept.  seeds and
+ * res (the results of bsw_extend_seeds*_device for those seeds) are device
+ * arrays of n entries; keep (device, n bytes) receives 1 for a kept seed,
+ * 0 for a dropped one.  stream and async as for bsw_extend_batch_device. */
+int bsw_filter_seeds_device(bsw_ctx* ctx, const bsw_seed* seeds, int64_t n,
+                            const bsw_seed_result* res, uint8_t* keep, void* stream,
+                            int32_t async);
+
 /* Autotuner of the seed driver: as bsw_ctx_tune, with whole seed calls
  * (arguments as bsw_extend_seeds_device, blocking, on the context's
  * stream) as the unit that is timed.  The winner is the launch shape of

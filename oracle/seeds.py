@@ -30,6 +30,18 @@ N3  A side with nothing to extend (qb = 0, or qe = len(read)) is skipped:
 Outputs per seed: score; read interval [qbeg, qend); reference interval
 [rbeg, rend); how = left choice | right choice << 2 with 0 = local end,
 1 = read end, 2 = nothing to extend.
+
+``filter_seeds`` is the step Sec. 5.3.2 puts after extending every seed:
+dropping the seeds the sequential mapper would not have extended, because
+an alignment it had already produced from the same chain covers them.
+
+F1  A chain is a run of consecutive seeds with the same read, in the order
+    given (the mapper's order within a chain, best seed first).
+F2  Walking a chain in that order, a seed is dropped when an earlier seed
+    of the chain that was kept has an extension whose read interval
+    [qbeg, qend) contains the seed's [qb, qe) and whose reference interval
+    [rbeg, rend) contains the seed's [rb, rb + qe - qb); otherwise it is
+    kept.  The first seed of a chain is always kept.
 """
 from __future__ import annotations
 
@@ -120,3 +132,32 @@ def extend_seeds(reads, read_off, ref, seeds, scoring, n_threads=0):
         out[k]["score"], out[k]["qend"], out[k]["rend"] = sc, qend, rend
         out[k]["how"] |= how << 2
     return out
+
+
+def filter_seeds(seeds, results):
+    """Keep flags (uint8, 1 = kept) of the seeds after extension (F1, F2)."""
+    seeds = np.asarray(seeds, dtype=SEED_DTYPE)
+    results = np.asarray(results, dtype=SEED_RESULT_DTYPE)
+    keep = np.zeros(len(seeds), dtype=np.uint8)
+    start = 0
+    while start < len(seeds):
+        end = start
+        while end < len(seeds) and seeds[end]["read"] == seeds[start]["read"]:
+            end += 1
+        kept = []
+        for k in range(start, end):
+            s = seeds[k]
+            qb, qe, rb = int(s["qb"]), int(s["qe"]), int(s["rb"])
+            re = rb + qe - qb
+            covered = False
+            for j in kept:
+                r = results[j]
+                if (int(r["qbeg"]) <= qb and qe <= int(r["qend"]) and
+                        int(r["rbeg"]) <= rb and re <= int(r["rend"])):
+                    covered = True
+                    break
+            if not covered:
+                kept.append(k)
+                keep[k] = 1
+        start = end
+    return keep

@@ -177,6 +177,9 @@ def lib():
         L.bsw_extend_batch_device_noalloc.argtypes = [
             _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP,
             ctypes.POINTER(Params), ctypes.c_int32, _VP, _VP, _VP, ctypes.c_int32]
+        L.bsw_filter_seeds_device.restype = ctypes.c_int
+        L.bsw_filter_seeds_device.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP, _VP,
+                                              ctypes.c_int32]
         L.bsw_ctx_shape.restype = ctypes.c_int
         L.bsw_ctx_shape.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.bsw_ctx_last_work.restype = ctypes.c_int
@@ -335,6 +338,15 @@ class Context:
             dev["ref"].data_ptr(), rev.data_ptr() if rev is not None else None,
             dev["ref"].numel(), dev["seeds"].data_ptr(), n, params, out.data_ptr(), s,
             1 if async_ else 0))
+
+    def filter_seeds_device(self, seeds, res, keep, stream=None, async_=False):
+        """Keep flags after extending every seed (``bsw_filter_seeds_device``):
+        seeds and res torch tensors of SEED_DTYPE / SEED_RESULT_DTYPE bytes,
+        keep a uint8 tensor of one byte per seed."""
+        n = seeds.numel() // SEED_DTYPE.itemsize
+        s = stream.cuda_stream if stream is not None else None
+        _check(lib().bsw_filter_seeds_device(self._h, seeds.data_ptr(), n, res.data_ptr(),
+                                             keep.data_ptr(), s, 1 if async_ else 0))
 
     def tune_seeds(self, dev, scoring, out, reps=2):
         """Autotune the seed driver's launch shape on a device seed workload

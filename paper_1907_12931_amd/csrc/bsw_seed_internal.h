@@ -48,4 +48,7 @@ void launch_seed_finish(int64_t n, const SeedPart* part, const bsw_result* rres,
                         const Status* sts, const Status* rst, int32_t bonus,
                         bsw_seed_result* out, hipStream_t s);
 
+void launch_seed_filter(const bsw_seed* seeds, int64_t n, const bsw_seed_result* res,
+                        uint8_t* keep, hipStream_t s);
+
 }  // namespace bsw

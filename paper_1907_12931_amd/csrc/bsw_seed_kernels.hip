@@ -9,6 +9,8 @@
 //                  are plain slices of the reversed buffers)
 //   k_seed_mid     the end kept after the left side and the right side's h0
 //   k_seed_finish  the end kept after the right side, and the output records
+//   k_seed_filter  after extension: the seeds an alignment of their chain
+//                  already covers (Sec. 5.3.2 extends every seed first)
 // One thread per seed in every per-seed kernel; grid-stride loops.
 #include <hip/hip_runtime.h>
 
@@ -248,6 +250,40 @@ void launch_seed_finish(int64_t n, const SeedPart* part, const bsw_result* rres,
                         bsw_seed_result* out, hipStream_t s) {
   hipLaunchKernelGGL(k_seed_finish, dim3(grid_for(n, 1, 8192)), dim3(256), 0, s, n, part,
                      rres, sts, rst, bonus, out);
+}
+
+// The filter after extending every seed (Sec. 5.3.2).  A chain is a run of
+// consecutive seeds of one read; the thread at a chain's first seed walks
+// it in order and drops a seed when an earlier kept seed's extension
+// contains it in the read ([qbeg, qend) holds [qb, qe)) and in the
+// reference ([rbeg, rend) holds [rb, rb + qe - qb)); the first is kept.
+__global__ void k_seed_filter(const bsw_seed* __restrict__ seeds, int64_t n,
+                              const bsw_seed_result* __restrict__ res,
+                              uint8_t* __restrict__ keep) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t read = seeds[k].read;
+    if (k > 0 && seeds[k - 1].read == read) continue;  // not a chain start
+    for (int64_t j = k; j < n && seeds[j].read == read; ++j) {
+      const bsw_seed sj = seeds[j];
+      const int64_t re = sj.rb + (sj.qe - sj.qb);
+      bool covered = false;
+      for (int64_t i = k; i < j && !covered; ++i) {
+        if (!keep[i]) continue;
+        const bsw_seed_result& r = res[i];
+        covered = r.qbeg <= sj.qb && sj.qe <= r.qend && r.rbeg <= sj.rb && re <= r.rend;
+      }
+      keep[j] = covered ? 0 : 1;
+    }
+  }
+}
+
+void launch_seed_filter(const bsw_seed* seeds, int64_t n, const bsw_seed_result* res,
+                        uint8_t* keep, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_seed_filter, dim3((unsigned)blocks), dim3(256), 0, s, seeds, n, res, keep);
 }
 
 }  // namespace bsw

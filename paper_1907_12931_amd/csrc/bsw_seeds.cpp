@@ -299,6 +299,31 @@ int bsw_extend_seeds_device(bsw_ctx* c, const uint8_t* reads, uint64_t reads_len
   return seed_done(c);
 }
 
+// The filter has no status to read back: nothing is left to do once its
+// stream has drained.
+static int filter_done(bsw_ctx*) { return BSW_OK; }
+
+int bsw_filter_seeds_device(bsw_ctx* c, const bsw_seed* seeds, int64_t n,
+                            const bsw_seed_result* res, uint8_t* keep, void* stream,
+                            int32_t async) {
+  if (!c) return set_error(BSW_EINVAL, "ctx is NULL");
+  if (int rc0 = ctx_check_idle(c)) return rc0;
+  if (n < 0) return set_error(BSW_EINVAL, "n = %lld out of range", (long long)n);
+  if (n == 0) return BSW_OK;
+  if (!seeds || !res || !keep) return set_error(BSW_EINVAL, "a required device pointer is NULL");
+  int rc = ctx_set_device(c);
+  if (rc) return rc;
+  hipStream_t s = stream ? (hipStream_t)stream : ctx_stream(c);
+  launch_seed_filter(seeds, n, res, keep, s);
+  HIPCHK(hipGetLastError());
+  if (async) {
+    ctx_set_pending(c, s, filter_done);
+    return BSW_OK;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return BSW_OK;
+}
+
 int bsw_extend_seeds(bsw_ctx* c, const uint8_t* reads, const uint64_t* read_off,
                      int64_t n_reads, const uint8_t* ref, uint64_t ref_len,
                      const bsw_seed* seeds, int64_t n, const bsw_params* params,

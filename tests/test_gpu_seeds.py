@@ -197,3 +197,62 @@ def test_seed_tuner_keeps_results_and_caches_its_own_entry(bsw, oracle_lib, tmp_
         c2.extend_seeds_device(dev, w["scoring"], out)
         assert_same(out.cpu().numpy().view(bsw.SEED_RESULT_DTYPE), want, "cached shape")
         assert c2.tune_info() == pairs_shape
+
+
+def filter_device(bsw, ctx, seeds, res, async_=False):
+    import torch
+    n = len(seeds)
+    sd = torch.from_numpy(np.ascontiguousarray(seeds).view(np.uint8).copy()).cuda()
+    rs = torch.from_numpy(np.ascontiguousarray(res).view(np.uint8).copy()).cuda()
+    keep = torch.full((max(n, 1),), 0x5a, dtype=torch.uint8, device="cuda")
+    ctx.filter_seeds_device(sd, rs, keep, async_=async_)
+    if async_:
+        ctx.wait()
+    return keep[:n].cpu().numpy()
+
+
+@pytest.mark.parametrize("max_seeds,async_", [(3, False), (12, True)])
+def test_filter_matches_reference(bsw, ctx, oracle_lib, max_seeds, async_):
+    from oracle import seeds as oseeds
+    w = synth.seed_workload(4000, seed=17, ref_len=300_000, max_seeds=max_seeds)
+    res = reference(w)
+    want = oseeds.filter_seeds(w["seeds"], res)
+    got = filter_device(bsw, ctx, w["seeds"], res, async_=async_)
+    print("seeds", len(want), "dropped", int((want == 0).sum()), flush=True)
+    assert (want == 0).sum() > 0 and want.sum() > 0
+    bad = np.nonzero(got != want)[0]
+    assert len(bad) == 0, f"{len(bad)} keep flags differ; first seed {bad[0]}"
+
+
+def test_filter_after_device_extension(bsw, ctx, oracle_lib):
+    # the flags of the whole device path (extend, then filter) on its own
+    # results equal the reference's flags on the reference's results
+    from oracle import seeds as oseeds
+    w = synth.seed_workload(2500, seed=18, max_seeds=8)
+    got_res = run_device(bsw, ctx, w, with_rev=True)
+    want = oseeds.filter_seeds(w["seeds"], reference(w))
+    assert np.array_equal(filter_device(bsw, ctx, w["seeds"], got_res), want)
+
+
+def test_filter_hand_cases(bsw, ctx):
+    from oracle import seeds as oseeds
+    sd = np.zeros(9, dtype=synth.SEED_FIELDS)
+    res = np.zeros(9, dtype=bsw.SEED_RESULT_DTYPE)
+    rows = [  # read, qb, qe, rb | qbeg, qend, rbeg, rend
+        (0, 10, 40, 110, 0, 100, 100, 200),
+        (0, 20, 30, 120, 0, 0, 0, 0),      # inside seed 0's extension: dropped
+        (0, 20, 30, 500, 5, 50, 490, 540),  # same read interval, other place: kept
+        (0, 60, 99, 160, 0, 0, 0, 0),       # inside 0 (ends at qend, rend): dropped
+        (0, 60, 101, 160, 0, 0, 0, 0),      # one past qend: kept
+        (1, 20, 30, 120, 0, 0, 0, 0),       # new chain: first seed kept
+        (1, 20, 30, 120, 0, 0, 0, 0),       # empty extension covers nothing: kept
+        (2, 0, 0, 7, 0, 1, 7, 8),           # zero-length seed: kept (first)
+        (2, 0, 0, 7, 0, 0, 0, 0),           # empty seed inside [0,1) x [7,8): dropped
+    ]
+    for k, (rd, qb, qe, rb, a, b, c, d) in enumerate(rows):
+        sd[k]["read"], sd[k]["qb"], sd[k]["qe"], sd[k]["rb"], sd[k]["h0"] = rd, qb, qe, rb, 1
+        res[k]["qbeg"], res[k]["qend"], res[k]["rbeg"], res[k]["rend"] = a, b, c, d
+    want = oseeds.filter_seeds(sd, res)
+    assert list(want) == [1, 0, 1, 0, 1, 1, 1, 1, 0]
+    assert list(filter_device(bsw, ctx, sd, res)) == list(want)
+    assert len(filter_device(bsw, ctx, sd[:0], res[:0])) == 0

@@ -172,3 +172,71 @@ def test_reference_invariants_on_synthetic_reads(seeds_mod):
     # every choice occurs on read-shaped data
     for side in (left, right):
         assert {0, 1, 2} <= set(np.unique(side).tolist())
+
+
+# ---------------------------------------------------------------------------
+# the filter after extending every seed (Sec. 5.3.2)
+
+def _seed(read, qb, qe, rb, h0=20):
+    return (read, qb, qe, h0, rb)
+
+
+def _res(qbeg, qend, rbeg, rend, score=50):
+    return (score, qbeg, qend, 0, rbeg, rend)
+
+
+def test_filter_hand_cases():
+    """Hand-made chains: the first seed of a read is kept; a later seed inside
+    a kept extension (read and reference) is dropped; one outside either
+    interval, on another read, or only inside a dropped seed's extension is
+    kept."""
+    from oracle import seeds as osd
+    S = np.array([
+        _seed(0, 10, 40, 1010),   # kept: first of read 0
+        _seed(0, 50, 70, 1050),   # dropped: inside seed 0's extension
+        _seed(0, 50, 70, 5050),   # kept: same read interval, other reference place
+        _seed(1, 0, 30, 2000),    # kept: first of read 1
+        _seed(1, 35, 60, 2035),   # kept: read end 60 past the extension's 50
+        _seed(1, 40, 45, 2040),   # dropped: inside the extension of seed 4
+        _seed(2, 5, 25, 300),     # kept: first of read 2
+    ], dtype=osd.SEED_DTYPE)
+    R = np.array([
+        _res(0, 151, 1000, 1151),
+        _res(0, 151, 1000, 1151),   # (a dropped seed's extension never covers)
+        _res(40, 100, 5040, 5100),
+        _res(0, 50, 2000, 2050),
+        _res(30, 151, 2030, 2151),
+        _res(0, 151, 0, 10**9),
+        _res(0, 151, 295, 446),
+    ], dtype=osd.SEED_RESULT_DTYPE)
+    assert osd.filter_seeds(S, R).tolist() == [1, 0, 1, 1, 1, 0, 1]
+    # boundaries are inclusive of the extension's ends
+    S2 = np.array([_seed(3, 0, 10, 100), _seed(3, 0, 10, 100), _seed(3, 1, 11, 101)],
+                  dtype=osd.SEED_DTYPE)
+    R2 = np.array([_res(0, 10, 100, 110)] * 3, dtype=osd.SEED_RESULT_DTYPE)
+    assert osd.filter_seeds(S2, R2).tolist() == [1, 0, 1]
+    assert osd.filter_seeds(S2[:0], R2[:0]).tolist() == []
+
+
+def test_filter_on_synthetic_reads(oracle_lib):
+    """On reads with several seeds: the first seed of every read is kept,
+    every later kept seed is outside every earlier kept extension of its
+    read, every dropped seed inside one, and some seeds are dropped."""
+    from oracle import seeds as osd
+    w = synth.seed_workload(n_reads=300, seed=17)
+    res = osd.extend_seeds(w["reads"], w["read_off"], w["ref"], w["seeds"], w["scoring"])
+    keep = osd.filter_seeds(w["seeds"], res)
+    S = w["seeds"]
+    assert keep.dtype == np.uint8 and set(np.unique(keep)) <= {0, 1}
+    dropped = 0
+    for k in range(len(S)):
+        earlier = [j for j in range(k) if S[j]["read"] == S[k]["read"] and keep[j]]
+        if k == 0 or S[k - 1]["read"] != S[k]["read"]:
+            assert keep[k] == 1
+        inside = any(res[j]["qbeg"] <= S[k]["qb"] and S[k]["qe"] <= res[j]["qend"] and
+                     res[j]["rbeg"] <= S[k]["rb"] and
+                     S[k]["rb"] + S[k]["qe"] - S[k]["qb"] <= res[j]["rend"]
+                     for j in earlier)
+        assert keep[k] == (0 if inside else 1)
+        dropped += 1 - int(keep[k])
+    assert dropped > 0
