@@ -130,16 +130,9 @@ int check_params(const bsw_params* params, int32_t n_params) {
   if (!params) return fail(BSW_EINVAL, "params is NULL");
   if (n_params < 1 || n_params > 256)
     return fail(BSW_EINVAL, "n_params = %d (must be 1..256)", n_params);
-  for (int i = 0; i < n_params; ++i) {
-    const bsw_params& p = params[i];
-    if (p.o_del < 0 || p.o_ins < 0 || p.o_del > BSW_MAX_GAP || p.o_ins > BSW_MAX_GAP)
-      return fail(BSW_EINVAL, "params[%d]: gap open must be 0..%d", i, BSW_MAX_GAP);
-    if (p.e_del < 1 || p.e_ins < 1 || p.e_del > BSW_MAX_GAP || p.e_ins > BSW_MAX_GAP)
-      return fail(BSW_EINVAL, "params[%d]: gap extend must be 1..%d", i, BSW_MAX_GAP);
-    if (p.w < 0) return fail(BSW_EINVAL, "params[%d]: w < 0", i);
-    if (p.end_bonus < 0 || p.end_bonus > BSW_MAX_BONUS)
-      return fail(BSW_EINVAL, "params[%d]: end_bonus out of range", i);
-  }
+  for (int i = 0; i < n_params; ++i)
+    if (const char* why = params_problem(params[i]))
+      return fail(BSW_EINVAL, "params[%d]: %s", i, why);
   return BSW_OK;
 }
 
@@ -509,64 +502,14 @@ std::string tune_key(const bsw_ctx* c, int wmax, bool sym, int kind) {
   return k;
 }
 
-std::vector<std::pair<std::string, std::string>> cache_read(const char* path) {
-  std::vector<std::pair<std::string, std::string>> e;
-  FILE* f = std::fopen(path, "r");
-  if (!f) return e;
-  char line[512];
-  while (std::fgets(line, sizeof line, f)) {
-    const char* a = std::strchr(line, '"');
-    const char* b = a ? std::strchr(a + 1, '"') : nullptr;
-    const char* v = b ? std::strchr(b, '{') : nullptr;
-    const char* z = v ? std::strchr(v, '}') : nullptr;
-    if (a && b && v && z) e.emplace_back(std::string(a + 1, b), std::string(v, z + 1));
-  }
-  std::fclose(f);
-  return e;
-}
-
 bool cache_lookup(const char* path, const std::string& key, Tune* t) {
-  for (auto& kv : cache_read(path)) {
-    if (kv.first != key) continue;
-    Tune x;
-    double ms = 0;
-    if (std::sscanf(kv.second.c_str(),
-                    "{\"nside\": %d, \"occ8\": %d, \"spec16\": %d, \"wave32\": %d, "
-                    "\"ms\": %lf}",
-                    &x.nside, &x.occ8, &x.spec16, &x.wave32, &ms) != 5)
-      return false;
-    if (x.nside < 1 || x.nside > bsw_ctx::NSIDE || x.occ8 < 1 || x.occ8 > 100 ||
-        (x.spec16 != 0 && x.spec16 != 1) || x.wave32 < 32 || x.wave32 > 512)
-      return false;
-    *t = x;
-    return true;
-  }
+  for (auto& kv : cache_read(path))
+    if (kv.first == key) return parse_tune(kv.second, bsw_ctx::NSIDE, t);
   return false;
 }
 
 int cache_store(const char* path, const std::string& key, const Tune& t, double ms) {
-  auto e = cache_read(path);
-  char v[160];
-  std::snprintf(v, sizeof v,
-                "{\"nside\": %d, \"occ8\": %d, \"spec16\": %d, \"wave32\": %d, \"ms\": %.3f}",
-                t.nside, t.occ8, t.spec16, t.wave32, ms);
-  bool found = false;
-  for (auto& kv : e)
-    if (kv.first == key) {
-      kv.second = v;
-      found = true;
-    }
-  if (!found) e.emplace_back(key, v);
-  const std::string tmp = std::string(path) + ".tmp";
-  FILE* f = std::fopen(tmp.c_str(), "w");
-  if (!f) return fail(BSW_EINVAL, "cannot write the tune cache %s", tmp.c_str());
-  std::fprintf(f, "{\n");
-  for (size_t i = 0; i < e.size(); ++i)
-    std::fprintf(f, " \"%s\": %s%s\n", e[i].first.c_str(), e[i].second.c_str(),
-                 i + 1 < e.size() ? "," : "");
-  std::fprintf(f, "}\n");
-  const bool ok = std::fclose(f) == 0;
-  if (!ok || std::rename(tmp.c_str(), path) != 0)
+  if (!cache_put(path, key, format_tune(t, ms)))
     return fail(BSW_EINVAL, "cannot write the tune cache %s", path);
   return BSW_OK;
 }
@@ -1271,18 +1214,23 @@ int bsw_extend_batch(bsw_ctx* c, int64_t n, const uint8_t* q, const uint64_t* q_
   if (rc) return rc;
   if (!q_off || !t_off || !h0 || !out) return fail(BSW_EINVAL, "a required pointer is NULL");
   // host-side validation of every pair before anything is staged
-  for (int64_t k = 0; k < n; ++k) {
-    if (q_off[k + 1] < q_off[k] || t_off[k + 1] < t_off[k] ||
-        q_off[k + 1] - q_off[k] > BSW_MAX_LEN || t_off[k + 1] - t_off[k] > BSW_MAX_LEN)
-      return fail(BSW_EINVAL, "pair %lld: bad offsets or length > %d", (long long)k, BSW_MAX_LEN);
-    if (h0[k] < 1 || h0[k] > BSW_MAX_H0)
-      return fail(BSW_EINVAL, "pair %lld: h0 = %d out of range", (long long)k, h0[k]);
-    if (param_id && param_id[k] >= n_params)
-      return fail(BSW_EINVAL, "pair %lld: param_id %d >= n_params", (long long)k, param_id[k]);
-    for (uint64_t x = q_off[k]; x < q_off[k + 1]; ++x)
-      if (q[x] > 4) return fail(BSW_EINVAL, "pair %lld: query code > 4", (long long)k);
-    for (uint64_t x = t_off[k]; x < t_off[k + 1]; ++x)
-      if (t[x] > 4) return fail(BSW_EINVAL, "pair %lld: target code > 4", (long long)k);
+  int why = PF_NONE;
+  const int64_t k = first_bad_pair(n, q, q_off, t, t_off, h0, param_id, n_params, &why);
+  if (k >= 0) {
+    switch (why) {
+      case PF_OFFSETS:
+        return fail(BSW_EINVAL, "pair %lld: bad offsets, length > %d or sequence NULL",
+                    (long long)k, BSW_MAX_LEN);
+      case PF_H0:
+        return fail(BSW_EINVAL, "pair %lld: h0 = %d out of range", (long long)k, h0[k]);
+      case PF_PID:
+        return fail(BSW_EINVAL, "pair %lld: param_id %d >= n_params", (long long)k,
+                    param_id[k]);
+      case PF_QCODE:
+        return fail(BSW_EINVAL, "pair %lld: query code > 4", (long long)k);
+      default:
+        return fail(BSW_EINVAL, "pair %lld: target code > 4", (long long)k);
+    }
   }
   if ((rc = set_device(c))) return rc;
   // stage: q bytes, t bytes, rebased offsets, h0, param_id

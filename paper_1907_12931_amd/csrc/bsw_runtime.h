@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/bsw.h"
+#include "bsw_hostutil.h"
 #include "bsw_internal.h"
 
 namespace bsw {
@@ -27,19 +28,6 @@ struct Args {
   const uint64_t* q_end;
   const uint64_t* t_end;
   bool codes_checked;  // the sequence bytes were validated beforehand
-};
-
-// Launch shapes of the batched path that the tuner chooses.
-struct Tune {
-  int nside = 4;    // side streams the classes are spread over (1..4)
-  int occ8 = 100;   // percent of the resident groups per CU for 8-bit classes
-  int spec16 = 1;   // try pairs whose bound needs 16 bits at 8 bits first
-  int wave32 = 64;  // 32-bit classes with a query cap >= this run one pair
-                    // per wave (wave mode); the others one pair per lane
-                    // (512: every 32-bit class in lane mode)
-  bool operator==(const Tune& o) const {
-    return nside == o.nside && occ8 == o.occ8 && spec16 == o.spec16 && wave32 == o.wave32;
-  }
 };
 
 // Workload kinds with a shape of their own: pair batches, and the BSW

@@ -341,31 +341,15 @@ int bsw_extend_seeds(bsw_ctx* c, const uint8_t* reads, const uint64_t* read_off,
   if (ref_len > (1ull << 48)) return set_error(BSW_EINVAL, "ref_len above 2^48");
   int rc = ctx_set_params(c, params, 1);
   if (rc) return rc;
-  for (int64_t i = 0; i < n_reads; ++i)
-    if (read_off[i + 1] < read_off[i] || read_off[i + 1] - read_off[i] > BSW_MAX_LEN)
-      return set_error(BSW_EINVAL, "read %lld: bad offsets or length > %d", (long long)i,
-                       BSW_MAX_LEN);
+  if (const int64_t i = first_bad_read(read_off, n_reads); i >= 0)
+    return set_error(BSW_EINVAL, "read %lld: bad offsets or length > %d", (long long)i,
+                     BSW_MAX_LEN);
   const uint64_t r0 = read_off[0], reads_len = read_off[n_reads] - r0;
   if (reads_len && !reads) return set_error(BSW_EINVAL, "reads is NULL");
-  const int64_t w = params->w;
-  for (int64_t k = 0; k < n; ++k) {
-    const bsw_seed& sd = seeds[k];
-    bool ok = sd.read >= 0 && sd.read < n_reads;
-    const int64_t len = ok ? (int64_t)(read_off[sd.read + 1] - read_off[sd.read]) : 0;
-    ok = ok && sd.qb >= 0 && sd.qb <= sd.qe && sd.qe <= len && sd.h0 >= 1 &&
-         sd.h0 <= BSW_MAX_H0 && sd.rb >= 0 && (uint64_t)sd.rb <= ref_len &&
-         (uint64_t)(sd.qe - sd.qb) <= ref_len - (uint64_t)sd.rb;
-    if (ok) {
-      const int64_t lt = std::min<int64_t>(sd.rb, (int64_t)sd.qb + w);
-      const uint64_t re = (uint64_t)sd.rb + (uint64_t)(sd.qe - sd.qb);
-      const uint64_t rt = std::min<uint64_t>(ref_len - re, (uint64_t)(len - sd.qe) + w);
-      ok = lt <= BSW_MAX_LEN && rt <= (uint64_t)BSW_MAX_LEN;
-    }
-    if (!ok)
-      return set_error(BSW_EINVAL, "seed %lld is invalid (read index, interval, h0, "
-                       "reference range, or a window longer than %d)", (long long)k,
-                       BSW_MAX_LEN);
-  }
+  if (const int64_t k = first_bad_seed(seeds, n, read_off, n_reads, ref_len, params->w); k >= 0)
+    return set_error(BSW_EINVAL, "seed %lld is invalid (read index, interval, h0, "
+                     "reference range, or a window longer than %d)", (long long)k,
+                     BSW_MAX_LEN);
   if ((rc = ctx_set_device(c))) return rc;
   SeedState* S;
   if ((rc = seed_state(c, &S))) return rc;

@@ -45,48 +45,6 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// First-fit allocator over the arena, with coalescing of free neighbours.
-class Arena {
- public:
-  void reset(size_t bytes) {
-    free_.clear();
-    free_[0] = bytes;
-    size_ = bytes;
-  }
-  bool alloc(size_t bytes, size_t* at) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < bytes) continue;
-      *at = it->first;
-      const size_t rest = it->second - bytes;
-      const size_t next = it->first + bytes;
-      free_.erase(it);
-      if (rest) free_[next] = rest;
-      return true;
-    }
-    return false;
-  }
-  void release(size_t at, size_t bytes) {
-    auto it = free_.emplace(at, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t size() const { return size_; }
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t size_ = 0;
-};
-
 enum ReqState { QUEUED, ADMITTED, RUNNING, DONE };
 
 struct Req {
