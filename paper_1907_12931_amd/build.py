@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsw.so")
 SOURCES = ["bsw_kernels.hip", "bsw_seed_kernels.hip", "bsw_sal_kernels.hip", "bsw_host.cpp",
            "bsw_fm_kernels.hip", "bsw_server.cpp", "bsw_seeds.cpp", "bsw_sal.cpp",
-           "bsw_fm.cpp", "bsw_peak.hip"]
+           "bsw_fm.cpp", "bsw_peak.hip", "bsw_lanev_s.hip", "bsw_lanev_m.hip",
+           "bsw_lanev_l.hip", "bsw_lanev_x.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -26,7 +27,7 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     from concurrent.futures import ThreadPoolExecutor
     cmds, objs = [], []
     for src in SOURCES:
