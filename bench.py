@@ -72,6 +72,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# the extension kernels' sources (a profile taken on other sources no
+# longer describes them)
+BSW_KERNEL_SOURCES = ["bsw_kernels.hip", "bsw_device.h", "bsw_internal.h", "bsw_lanev.h",
+                      "bsw_lanev_impl.h", "bsw_lanev_s.hip", "bsw_lanev_m.hip",
+                      "bsw_lanev_l.hip", "bsw_lanev_x.hip"]
+
+
 def traffic_from_profile(kernel, work, profile="bsw"):
     """HBM bytes per launch of a kernel from the committed counter profile
     (FETCH_SIZE + WRITE_SIZE, calibrated on a plain streaming kernel), if
@@ -80,7 +87,7 @@ def traffic_from_profile(kernel, work, profile="bsw"):
     suffix-array lookup); else None."""
     import hashlib
     import re
-    srcs, work_field = {"bsw": (["bsw_kernels.hip"], "cells_per_launch"),
+    srcs, work_field = {"bsw": (BSW_KERNEL_SOURCES, "cells_per_launch"),
                         "sal": (["bsw_sal_kernels.hip"], "alg_bytes_per_launch"),
                         "fm": (["bsw_fm_kernels.hip", "bsw_fm_device.h"],
                                "alg_bytes_per_launch")}[profile]

@@ -192,10 +192,10 @@ __device__ __forceinline__ void sweep_row(int c0, uint2 (&r)[NQ], const uint32_t
 #undef BSW_SWEEP_CASES8
 #undef BSW_SWEEP_CASE
 
-// Waves per SIMD the register budget is set for: three for the classes
-// whose row fits 168 registers, two above.
+// Waves per SIMD the register budget is set for (512 registers per lane
+// of a SIMD): four up to 96 columns, three up to 160, two above.
 template <int CAP> struct LaneVRegs {
-  static constexpr int WAVES = CAP <= 128 ? 3 : 2;
+  static constexpr int WAVES = CAP <= 96 ? 4 : (CAP <= 160 ? 3 : 2);
 };
 
 template <int CAP, bool SYM>
@@ -218,6 +218,8 @@ k_lanev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
   const long long begin = range[0], count = range[1];
   const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
   uint32_t tile = blockIdx.x;
+  // settled cells and lane-cells stepped through, summed over the wave's
+  // tiles (wave-uniform, so that they take no vector registers)
   unsigned long long tile_cells_acc = 0, span_chunks = 0;
   uint2 r[NQ];
   uint32_t qv[NQW];
@@ -302,8 +304,12 @@ k_lanev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
       }
     }
 
-    int best = h0, bi = -1, bj = -1, gbest = -1, gi = -1, moff = 0;
-    int beg = 0, end = Lq, rows = 0, stop = 0, cells = 0;
+    // bi + 1 and bj + 1 (row and column of the best cell, -1 before one)
+    // share a word, as do the stop reason and the rows entered (set at the
+    // stop)
+    int best = h0, gbest = -1, gi = -1, moff = 0;
+    uint32_t bij = 0;
+    int beg = 0, end = Lq, stoprows = 0, cells = 0;
     bool live = valid && Lt > 0;
     const uint8_t* ts = t + pd.to;
     // the score row of the next row and the target code of the one after,
@@ -320,7 +326,6 @@ k_lanev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
       const int eD = pp.eD[0];
       int hl = 0;
       if (live) {
-        ++rows;
         // band (Sec. 5.1 (a)); columns left of beg are read as zero below
         beg = imax(beg, i - wb);
         end = imin(imin(end, i + wb + 1), Lq);
@@ -365,18 +370,17 @@ k_lanev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         const uint32_t mk = imax((int)(mkey & 0xffffu), (int)(mkey >> 16));
         const int m = (int)(mk >> 8), mj = (int)(mk & 0xffu);
         if (m == 0) {
-          stop = 1;
+          stoprows = (1 << 16) | (i + 1);
           live = false;
         } else if (m > best) {
           best = m;
-          bi = i;
-          bj = mj;
+          bij = ((uint32_t)(i + 1) << 16) | (uint32_t)(mj + 1);
           moff = imax(moff, mj > i ? mj - i : i - mj);
         } else if (zd > 0) {
-          const int drift = (i - bi) - (mj - bj);
+          const int drift = (i - (int)(bij >> 16)) - (mj - (int)(bij & 0xffffu));
           const int drop = best - m - (drift > 0 ? drift * eD : -drift * pp.eI[0]);
           if (drop > zd) {
-            stop = 2;
+            stoprows = (2 << 16) | (i + 1);
             live = false;
           }
         }
@@ -417,25 +421,30 @@ k_lanev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         my_cells = (unsigned long long)cells;
         bsw_result res;
         res.score = best;
-        res.qle = bj + 1;
-        res.tle = bi + 1;
+        res.qle = (int)(bij & 0xffffu);
+        res.tle = (int)(bij >> 16);
         res.gtle = gi + 1;
         res.gscore = gbest;
         res.max_off = moff;
         out[pidx] = res;
         if (diag) {
           bsw_diag dg;
-          dg.rows = rows;
-          dg.stop = stop;
+          // a pair that never stopped entered every target row
+          dg.rows = stoprows ? (stoprows & 0xffff) : Lt;
+          dg.stop = stoprows >> 16;
           dg.cells = cells;
           diag[pidx] = dg;
         }
       }
     }
-    tile_cells_acc += my_cells;
+    {
+      const unsigned long long ws = wave_sum64(my_cells);
+      tile_cells_acc += ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(ws >> 32))
+                         << 32) |
+                        __builtin_amdgcn_readfirstlane((uint32_t)ws);
+    }
     if (!persist) break;
   }
-  tile_cells_acc = wave_sum64(tile_cells_acc);
   if (lane == 0 && tile_cells_acc) atomicAdd(cls_cells, tile_cells_acc);
   if (lane == 0 && span_chunks) atomicAdd(work_cells, span_chunks * 4ull * 64ull);
 #undef MIRW
