@@ -72,11 +72,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# the extension kernels' sources (a profile taken on other sources no
-# longer describes them)
-BSW_KERNEL_SOURCES = ["bsw_kernels.hip", "bsw_device.h", "bsw_internal.h", "bsw_lanev.h",
-                      "bsw_lanev_impl.h", "bsw_lanev_s.hip", "bsw_lanev_m.hip",
-                      "bsw_lanev_l.hip", "bsw_lanev_x.hip"]
+# the sources an extension kernel is built from (a profile taken on other
+# sources no longer describes it): the register-row kernel's own units, or
+# the main kernel file for every other one
+LANEV_SOURCES = ["bsw_device.h", "bsw_internal.h", "bsw_lanev.h", "bsw_lanev_impl.h",
+                 "bsw_lanev_s.hip", "bsw_lanev_m.hip", "bsw_lanev_l.hip", "bsw_lanev_x.hip"]
+KERNEL_SOURCES = ["bsw_kernels.hip", "bsw_device.h", "bsw_internal.h"]
+
+
+def bsw_sources(kernel):
+    return LANEV_SOURCES if "k_lanev" in kernel else KERNEL_SOURCES
 
 
 def traffic_from_profile(kernel, work, profile="bsw"):
@@ -87,7 +92,7 @@ def traffic_from_profile(kernel, work, profile="bsw"):
     suffix-array lookup); else None."""
     import hashlib
     import re
-    srcs, work_field = {"bsw": (BSW_KERNEL_SOURCES, "cells_per_launch"),
+    srcs, work_field = {"bsw": (bsw_sources(kernel), "cells_per_launch"),
                         "sal": (["bsw_sal_kernels.hip"], "alg_bytes_per_launch"),
                         "fm": (["bsw_fm_kernels.hip", "bsw_fm_device.h"],
                                "alg_bytes_per_launch")}[profile]
@@ -166,7 +171,7 @@ def serve(bsw, synth, batch, host, capacity, rho, n_requests, seed=3):
             for a, m in zip(starts.tolist(), sizes.tolist())]
     tickets = [None] * n_requests
     ready = threading.Semaphore(0)
-    with bsw.Server(batch["scorings"], hbm_budget=8 << 30) as srv:
+    with bsw.Server(batch["scorings"]) as srv:
         def waiter():
             for k in range(n_requests):
                 ready.acquire()

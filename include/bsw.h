@@ -267,25 +267,25 @@ const char* bsw_class_name(int32_t cls);
  * Serving (the paper's reorganisation of the work into large batches with
  * buffers reused across them, Sec. 3.2 and 5.3.1, applied to requests that
  * arrive over time).  A server owns one device arena of hbm_budget bytes
- * that holds the data of every admitted request (sequences, offsets, h0,
- * param_id and a status block) from admission until completion, and
- * max_inflight execution slots (each a context with its own streams and
- * workspace).  Requests are admitted strictly in arrival order while the
- * head request fits in the free arena space; admission copies the request
- * to the device and checks its codes there.  Whenever a slot is free, every
- * admitted request whose data is resident and valid joins one batch (up to
- * max_batch_pairs pairs), which runs the batched path; results are copied
- * back into each request's own output buffer.  A request's results equal
- * those of the same pairs run alone (pairs are independent).
+ * that holds the data of every admitted request (sequences, offsets, h0 and
+ * param_id) from admission until its batch has run, and max_inflight
+ * execution slots (each a context with its own stream and workspace).
+ * Requests are admitted strictly in arrival order while the head request
+ * fits in the free arena space.  Whenever a slot is free, the admitted
+ * requests join one batch (up to max_batch_pairs pairs): on the slot's own
+ * stream their data is copied to their regions, their codes are checked,
+ * and the batched path runs; results are copied back into each request's
+ * own output buffer.  A request's results equal those of the same pairs
+ * run alone (pairs are independent).
  * ---------------------------------------------------------------------- */
 typedef struct bsw_server bsw_server;
 
 typedef struct bsw_server_opts {
   int32_t device;
-  int32_t max_inflight;     /* slots (concurrent batches), 1..8; 0 = 2      */
+  int32_t max_inflight;     /* slots (concurrent batches), 1..8; 0 = 3      */
   int64_t max_batch_pairs;  /* pairs per batch cap; 0 = 4,194,304; a larger
                              * request runs as a batch of its own            */
-  size_t  hbm_budget;       /* arena for resident request data; 0 = 8 GiB   */
+  size_t  hbm_budget;       /* arena for resident request data; 0 = 16 GiB  */
   int32_t max_queued;       /* submitted, not yet admitted requests before
                              * bsw_server_submit returns BSW_EBUSY; 0 = 65536 */
   int32_t min_lane_bits;    /* as in bsw_ctx_opts                          */
@@ -318,12 +318,14 @@ void bsw_server_destroy(bsw_server* srv);
 /* Submit a request of n >= 1 pairs in host memory (same layout and rules
  * as bsw_extend_batch; param_id indexes the server's table).  Offsets,
  * lengths, h0 and param_id are checked here (BSW_EINVAL); the codes are
- * checked on the device at admission, and a bad code fails the request at
- * bsw_server_wait.  Returns BSW_ETOOBIG if the request needs more than the
- * whole arena, BSW_EBUSY if max_queued requests are waiting for admission.
- * On success *ticket identifies the request.  Every buffer of the request,
- * out and diag (nullable) included, must stay valid and unchanged until
- * bsw_server_wait has returned for the ticket. */
+ * checked on the device when the request's batch runs, and a bad code
+ * fails the request (alone) at bsw_server_wait.  Returns BSW_ETOOBIG if the
+ * request needs more than the whole arena, BSW_EBUSY if max_queued
+ * requests are waiting for admission.  On success *ticket identifies the
+ * request.  Arrays in pinned host memory (hipHostMalloc) are read by the
+ * device directly, the others are copied by the runtime.  Every buffer of
+ * the request, out and diag (nullable) included, must stay valid and
+ * unchanged until bsw_server_wait has returned for the ticket. */
 int bsw_server_submit(bsw_server* srv, int64_t n,
                       const uint8_t* q, const uint64_t* q_off,
                       const uint8_t* t, const uint64_t* t_off,

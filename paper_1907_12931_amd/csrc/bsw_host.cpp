@@ -457,15 +457,16 @@ int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan&
   if (ev) HIPCHK(hipEventRecord(c->ev[1], s));
   if (ev) HIPCHK(hipEventRecord(c->ev[2], s));
   c->n_launch = 0;
-  HIPCHK(hipEventRecord(c->fork_ev, s));
+  // nside = 0: every class on the call's stream, in order
   const int nside = c->tunes[c->kind].nside;
+  if (nside > 0) HIPCHK(hipEventRecord(c->fork_ev, s));
   for (int k = 0; k < nside; ++k) HIPCHK(hipStreamWaitEvent(c->side[k], c->fork_ev, 0));
   int order[NCLS], no = 0;
   for (int cls = CLS_W16 - 1; cls >= CLS_L8; --cls) order[no++] = cls;
   for (int cls = CLS_W16; cls < CLS_LONG; ++cls) order[no++] = cls;
   for (int oi = 0; oi < no; ++oi) {
     const int cls = order[oi];
-    hipStream_t ls = c->side[oi % nside];
+    hipStream_t ls = nside > 0 ? c->side[oi % nside] : s;
     if ((rc = begin_launch(c, cls | (wave_mode(c, cls) ? WAVE_TAG : 0), ls))) return rc;
     // pairs a narrow class cannot settle in its record width go to the
     // rerun list
@@ -528,6 +529,16 @@ void pick_tune(bsw_ctx* c, int wmax, bool sym) {
 // eagerly or as a graph.  The graph is captured on the first call with a
 // given set of pointers and shapes and replayed while they stay the same;
 // the scoring table is uploaded outside it, before every replay.
+// The side streams a shape uses, created on first need (before any graph
+// capture): a context that never uses them (a server slot) keeps every
+// class on its own stream and so holds one hardware queue, not five.
+int ensure_side(bsw_ctx* c, int nside) {
+  for (int k = 0; k < nside; ++k)
+    if (!c->side[k] && hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking) != hipSuccess)
+      return fail(BSW_EDEVICE, "cannot create a side stream");
+  return BSW_OK;
+}
+
 int run_batched(bsw_ctx* c, const Args& a, hipStream_t s) {
   int wmax;
   bool sym;
@@ -553,9 +564,11 @@ int run_batched(bsw_ctx* c, const Args& a, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(c->d_kp, c->h_kp, sizeof(KParams) * a.n_params,
                           hipMemcpyHostToDevice, s));
     c->graph_call = false;
+    if ((rc = ensure_side(c, c->tunes[c->kind].nside))) return rc;
     return enqueue_batched(c, a, w, p, sym, s);
   }
   pick_tune(c, wmax, sym);
+  if ((rc = ensure_side(c, c->tunes[c->kind].nside))) return rc;
   if ((rc = c->ws.ensure(L.total))) return rc;
   BatchedPlan p = plan_batched(c, wmax, sym);
   if ((rc = c->qtiles.ensure(p.qt_words * 4))) return rc;
@@ -817,6 +830,10 @@ int set_error(int code, const char* fmt, ...) {
   return code;
 }
 
+void ctx_set_side_streams(bsw_ctx* c, int nside) {
+  c->tunes[KIND_PAIRS].nside = nside < 0 ? 0 : (nside > bsw_ctx::NSIDE ? bsw_ctx::NSIDE : nside);
+}
+
 int ctx_set_params(bsw_ctx* c, const bsw_params* params, int32_t n_params) {
   const int rc = check_params(params, n_params);
   if (rc) return rc;
@@ -971,8 +988,6 @@ int bsw_ctx_create(bsw_ctx** out, const bsw_ctx_opts* opts) {
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = BSW_EDEVICE;
   if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess)
     rc = BSW_EDEVICE;
-  for (auto& st : c->side)
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) rc = BSW_EDEVICE;
   if (hipHostMalloc((void**)&c->h_kp, sizeof(KParams) * 256, 0) != hipSuccess ||
       hipHostMalloc((void**)&c->h_status, sizeof(Status), 0) != hipSuccess ||
       hipHostMalloc((void**)&c->h_cls, sizeof(int64_t) * 2 * NCLS, 0) != hipSuccess ||

@@ -311,19 +311,85 @@ __global__ void k_scatter(int64_t n, const uint64_t* __restrict__ q_off,
 // Request r covers batch pairs [tab[r].base, tab[r].base + tab[r].n); its
 // sequence bytes sit at byte offsets q_at / t_at from the common base and
 // its offset arrays are the caller's, taken relative to their first entry.
+// Copy of byte ranges from mapped host memory into device memory, one 4 KiB
+// chunk per workgroup step: every thread writes whole destination dwords
+// (destinations are 4-byte aligned, with at least 3 bytes of slack after
+// each range), each composed from the two aligned source dwords that
+// cover it; a source dword is read only if it holds a byte of the range,
+// so no read leaves the range's pages.
+__global__ void __launch_bounds__(256) k_gather(const CopySeg* __restrict__ segs, int ns,
+                                                unsigned long long nchunks) {
+  for (unsigned long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    int a = 0, b = ns - 1;
+    while (a < b) {
+      const int m = (a + b + 1) >> 1;
+      if (segs[m].chunk0 <= c) a = m; else b = m - 1;
+    }
+    const CopySeg sg = segs[a];
+    const unsigned long long off = (c - sg.chunk0) * 4096ull;
+    const uintptr_t s0 = (uintptr_t)sg.src;
+    const uintptr_t sal = s0 & ~(uintptr_t)3;
+    const uint32_t sh = (uint32_t)(s0 & 3);
+    const uintptr_t slim = s0 + sg.bytes;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const unsigned long long o = off + ((unsigned long long)k * 256 + threadIdx.x) * 4;
+      if (o >= sg.bytes) break;
+      const uintptr_t p0 = sal + o, p1 = p0 + 4;
+      const uint32_t w0 = *(const uint32_t*)p0;
+      const uint32_t w1 = p1 < slim ? *(const uint32_t*)p1 : 0u;
+      *(uint32_t*)(sg.dst + o) = __builtin_amdgcn_alignbyte(w1, w0, sh);
+    }
+  }
+}
+
+// The request of batch pair g: the last table entry whose base is <= g.
+__device__ __forceinline__ int req_of(const ReqSlice* __restrict__ tab, int m, int64_t g) {
+  int a = 0, b = m - 1;
+  while (a < b) {
+    const int c = (a + b + 1) >> 1;
+    if (tab[c].base <= g) a = c; else b = c - 1;
+  }
+  return a;
+}
+
+// Code check of a serving batch, one pair per thread: a request with a
+// byte > 4 in any of its pairs gets bad[a] = ~(its smallest such pair).
+__global__ void k_req_codes(const ReqSlice* __restrict__ tab, int m, int64_t n,
+                            const uint8_t* __restrict__ base,
+                            unsigned long long* __restrict__ bad) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int a = req_of(tab, m, g);
+    const ReqSlice& r = tab[a];
+    const int64_t i = g - r.base;
+    const uint8_t* qs = base + r.q_at + (r.q_off[i] - r.q_off[0]);
+    const uint8_t* ts = base + r.t_at + (r.t_off[i] - r.t_off[0]);
+    const uint64_t ql = r.q_off[i + 1] - r.q_off[i], tl = r.t_off[i + 1] - r.t_off[i];
+    bool ok = true;
+    for (uint64_t k = 0; k < ql && ok; ++k) ok = qs[k] <= 4;
+    for (uint64_t k = 0; k < tl && ok; ++k) ok = ts[k] <= 4;
+    if (!ok) atomicMax(&bad[a], ~(unsigned long long)i);
+  }
+}
+
 __global__ void k_assemble(const ReqSlice* __restrict__ tab, int m, int64_t n,
                            uint64_t* __restrict__ qb, uint64_t* __restrict__ qe,
                            uint64_t* __restrict__ tb, uint64_t* __restrict__ te,
-                           int32_t* __restrict__ h0, uint8_t* __restrict__ pid) {
+                           int32_t* __restrict__ h0, uint8_t* __restrict__ pid,
+                           const unsigned long long* __restrict__ bad) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;
        g += (int64_t)gridDim.x * blockDim.x) {
-    int a = 0, b = m - 1;  // last request with base <= g
-    while (a < b) {
-      const int c = (a + b + 1) >> 1;
-      if (tab[c].base <= g) a = c; else b = c - 1;
-    }
+    const int a = req_of(tab, m, g);
     const ReqSlice& r = tab[a];
     const int64_t i = g - r.base;
+    if (bad[a]) {  // a rejected request: empty pairs that read no byte
+      qb[g] = qe[g] = r.q_at;
+      tb[g] = te[g] = r.t_at;
+      h0[g] = 1;
+      pid[g] = 0;
+      continue;
+    }
     const uint64_t q0 = r.q_off[0], t0 = r.t_off[0];
     qb[g] = r.q_at + (r.q_off[i] - q0);
     qe[g] = r.q_at + (r.q_off[i + 1] - q0);
@@ -1546,13 +1612,28 @@ void launch_scatter(int64_t n, const uint64_t* q_off, const uint64_t* q_end,
                      t_off, t_end, h0, pid, keys, cursor, desc, st);
 }
 
+void launch_gather(const CopySeg* segs, int ns, unsigned long long nchunks, hipStream_t s) {
+  if (!nchunks) return;
+  const unsigned blocks = (unsigned)(nchunks < 1024 ? nchunks : 1024);
+  hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(256), 0, s, segs, ns, nchunks);
+}
+
+void launch_req_codes(const ReqSlice* tab, int m, int64_t n, const uint8_t* base,
+                      unsigned long long* bad, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_req_codes, dim3((unsigned)blocks), dim3(256), 0, s, tab, m, n, base, bad);
+}
+
 void launch_assemble(const ReqSlice* tab, int m, int64_t n, uint64_t* qb, uint64_t* qe,
-                     uint64_t* tb, uint64_t* te, int32_t* h0, uint8_t* pid, hipStream_t s) {
+                     uint64_t* tb, uint64_t* te, int32_t* h0, uint8_t* pid,
+                     const unsigned long long* bad, hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(256), 0, s, tab, m, n, qb, qe,
-                     tb, te, h0, pid);
+                     tb, te, h0, pid, bad);
 }
 
 void launch_lane(int cls, bool persist, unsigned blocks, const PairDesc* desc,

@@ -76,6 +76,9 @@ struct DevBuf {
 
 // Load a context's scoring table (validated).
 int ctx_set_params(bsw_ctx* c, const bsw_params* params, int32_t n_params);
+// Side streams the batched path spreads the classes over (0: all classes
+// on the call's stream; the context then keeps to one hardware queue).
+void ctx_set_side_streams(bsw_ctx* c, int nside);
 // Allocate a context's device buffers for calls of up to n pairs with its
 // current scoring table, so that such calls allocate nothing.
 int ctx_reserve(bsw_ctx* c, int64_t n, int32_t n_params);
@@ -142,7 +145,16 @@ void fm_state_free(FmState* s);
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
                   uint64_t bytes, hipStream_t s);
+// Copy the byte ranges segs[0 .. ns) (nchunks 4 KiB chunks in all) from
+// mapped host memory to the device.
+void launch_gather(const CopySeg* segs, int ns, unsigned long long nchunks, hipStream_t s);
+// Serving batches: flag (bad[a] = ~(first bad pair), else 0) every request
+// of the table with a sequence byte > 4, then gather the pairs of the
+// unflagged requests (a flagged request's pairs get no bytes).
+void launch_req_codes(const ReqSlice* tab, int m, int64_t n, const uint8_t* base,
+                      unsigned long long* bad, hipStream_t s);
 void launch_assemble(const ReqSlice* tab, int m, int64_t n, uint64_t* qb, uint64_t* qe,
-                     uint64_t* tb, uint64_t* te, int32_t* h0, uint8_t* pid, hipStream_t s);
+                     uint64_t* tb, uint64_t* te, int32_t* h0, uint8_t* pid,
+                     const unsigned long long* bad, hipStream_t s);
 
 }  // namespace bsw

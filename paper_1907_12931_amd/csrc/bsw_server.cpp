@@ -4,16 +4,18 @@
 // device work of the server and runs three steps in a loop:
 //  1. admission: the oldest waiting request is given a region of the arena
 //     when it fits (strict arrival order, so a large request is never
-//     overtaken); its data is copied to the device on the upload stream and
-//     its codes are checked there;
-//  2. completion: a slot whose batch has finished hands each request its
-//     results and releases the request's region;
-//  3. dispatch: a free slot takes every admitted request whose data is
-//     resident and valid, gathers their pairs into one batch on the device
-//     and runs the batched path over it.
-// Batches form from whatever is ready when a slot frees up, so new requests
-// join the work between batches while the other slots keep the GPU busy
-// (continuous batching at batch granularity).
+//     overtaken);
+//  2. completion: a slot whose batch has finished frees its requests'
+//     regions and is free again at once; a copier thread hands the results
+//     to each request;
+//  3. dispatch: a free slot takes every admitted request, copies their data
+//     to their regions on its own stream, checks their codes, gathers their
+//     pairs into one batch on the device and runs the batched path over it.
+// A slot's uploads run on its own stream, so they never wait behind the
+// other slot's kernels on a shared hardware queue; while one slot uploads,
+// the other computes.  Batches form from whatever is admitted when a slot
+// frees up, so new requests join the work between batches while the other
+// slots keep the GPU busy (continuous batching at batch granularity).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +27,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -60,17 +63,36 @@ struct Req {
   bsw_diag* diag = nullptr;
   uint64_t qbytes = 0, tbytes = 0;
   // region layout (offsets from the region start) and placement
-  size_t o_st = 0, o_q = 0, o_t = 0, o_qo = 0, o_to = 0, o_h0 = 0, o_pid = 0, bytes = 0;
+  size_t o_q = 0, o_t = 0, o_qo = 0, o_to = 0, o_h0 = 0, o_pid = 0, bytes = 0;
   size_t at = 0;
-  Status* h_st = nullptr;  // pinned copy of the device status after the code check
-  hipEvent_t ready = nullptr;
+  // the device's view of the request's arrays when they are in pinned host
+  // memory (read by k_gather), else null (copied with hipMemcpyAsync):
+  // query bytes, target bytes, q_off, t_off, h0, param_id
+  const uint8_t* dsrc[6] = {};
   ReqState state = QUEUED;
   int rc = BSW_OK;
   char err[160] = {0};
   Clock::time_point t_submit, t_admit, t_done;
 };
 
-enum SlotState { SLOT_FREE, SLOT_RUNNING, SLOT_COPYING };
+enum SlotState { SLOT_FREE, SLOT_RUNNING };
+
+// A pinned host buffer for a batch's results (and diagnostics).
+struct ResBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+// A finished batch whose results wait to be handed to its requests: the
+// slot that ran it and the requests' device regions are already free.
+struct Handoff {
+  std::vector<Req*> reqs;
+  ResBuf buf;
+  int64_t n = 0;
+  int rc = BSW_OK;
+  unsigned long long cells = 0;
+  std::string err;
+};
 
 struct Slot {
   bsw_ctx* ctx = nullptr;
@@ -83,11 +105,12 @@ struct Slot {
   // device: assembled batch arrays and the request table
   void* dev = nullptr;
   size_t dev_cap = 0;
-  // pinned host: request table and results of the batch
+  // pinned host: request table, and the results buffer of the running
+  // batch (taken from the server's pool at launch, handed on at completion)
   ReqSlice* h_tab = nullptr;
   int tab_cap = 0;
-  void* h_res = nullptr;
-  size_t h_res_cap = 0;
+  CopySeg* h_seg = nullptr;  // pinned: the batch's copy list (6 per request)
+  ResBuf res;
 };
 
 }  // namespace
@@ -97,15 +120,12 @@ struct bsw_server {
   std::vector<bsw_params> params;
   char* arena_base = nullptr;
   Arena arena;
-  hipStream_t up = nullptr;  // uploads and code checks
   std::deque<Slot> slots;  // a deque: slots hold atomics and never move
-  std::vector<hipEvent_t> free_events;
-  std::vector<Status*> free_status;
-  std::vector<Status*> status_blocks;  // pinned allocations (freed at the end)
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_copy;
-  std::deque<int> copy_q;  // finished slots whose results wait to be handed out
+  std::deque<Handoff> copy_q;  // finished batches whose results wait to be handed out
+  std::vector<ResBuf> res_pool;  // pinned result buffers not in use
   bool copier_stop = false;
   std::thread copier;
   std::deque<Req*> pending;   // submitted, waiting for admission
@@ -135,11 +155,9 @@ namespace {
                        "%s failed: %s", #expr, hipGetErrorString(e_));        \
   } while (0)
 
-// Bytes of a request's region: status, sequences, offsets, h0, param_id.
+// Bytes of a request's region: sequences, offsets, h0, param_id.
 void plan_region(Req* r) {
   size_t o = 0;
-  r->o_st = o;
-  o = align_up(o + sizeof(Status), 256);
   r->o_q = o;
   o = align_up(o + r->qbytes + 4, 256);
   r->o_t = o;
@@ -151,69 +169,57 @@ void plan_region(Req* r) {
   r->o_h0 = o;
   o = align_up(o + 4 * (size_t)r->n, 256);
   r->o_pid = o;
-  o = align_up(o + (size_t)r->n, 256);
+  o = align_up(o + (size_t)r->n + 4, 256);
   r->bytes = o;
 }
 
-// Pinned status records, allocated in blocks and reused.
-int take_status(bsw_server* v, Status** out) {
-  if (v->free_status.empty()) {
-    Status* blk = nullptr;
-    SRVCHK(hipHostMalloc((void**)&blk, sizeof(Status) * 64, 0));
-    v->status_blocks.push_back(blk);
-    for (int i = 0; i < 64; ++i) v->free_status.push_back(blk + i);
+// The device address of host memory the device can read (pinned and
+// mapped), else null.  A failed query leaves no error behind.
+const uint8_t* device_view(const void* p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
   }
-  *out = v->free_status.back();
-  v->free_status.pop_back();
-  return BSW_OK;
+  if (at.type != hipMemoryTypeHost || !at.devicePointer) return nullptr;
+  return (const uint8_t*)at.devicePointer;
 }
 
-int take_event(bsw_server* v, hipEvent_t* out) {
-  if (v->free_events.empty()) {
-    hipEvent_t e = nullptr;
-    SRVCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    v->free_events.push_back(e);
-  }
-  *out = v->free_events.back();
-  v->free_events.pop_back();
-  return BSW_OK;
-}
-
-// Copy an admitted request to its region and check its codes there; the
-// request's ready event follows the copy of its status to the host.
-int upload(bsw_server* v, Req* r) {
+// Queue an admitted request's data for its region: short ranges the device
+// can read go to the copy list (one k_gather for the batch), the others are
+// copied with hipMemcpyAsync on stream s (long ranges from pinned memory go
+// to the copy engines, which run beside the other slot's kernels).
+constexpr size_t GATHER_MAX = (size_t)1 << 20;
+int upload(bsw_server* v, Req* r, CopySeg* segs, int* ns, unsigned long long* chunks,
+           hipStream_t s) {
   char* base = v->arena_base + r->at;
-  Status* st = (Status*)(base + r->o_st);
-  uint8_t* dq = (uint8_t*)(base + r->o_q);
-  uint8_t* dt = (uint8_t*)(base + r->o_t);
-  uint64_t* dqo = (uint64_t*)(base + r->o_qo);
-  uint64_t* dto = (uint64_t*)(base + r->o_to);
-  int rc = take_status(v, &r->h_st);
-  if (rc) return rc;
-  if ((rc = take_event(v, &r->ready))) return rc;
-  hipStream_t s = v->up;
-  launch_fill((uint32_t*)st, sizeof(Status) / 4, s);
-  if (r->qbytes) SRVCHK(hipMemcpyAsync(dq, r->q + r->q_off[0], r->qbytes, hipMemcpyHostToDevice, s));
-  if (r->tbytes) SRVCHK(hipMemcpyAsync(dt, r->t + r->t_off[0], r->tbytes, hipMemcpyHostToDevice, s));
-  SRVCHK(hipMemcpyAsync(dqo, r->q_off, 8 * (size_t)(r->n + 1), hipMemcpyHostToDevice, s));
-  SRVCHK(hipMemcpyAsync(dto, r->t_off, 8 * (size_t)(r->n + 1), hipMemcpyHostToDevice, s));
-  SRVCHK(hipMemcpyAsync(base + r->o_h0, r->h0, 4 * (size_t)r->n, hipMemcpyHostToDevice, s));
-  if (r->pid)
-    SRVCHK(hipMemcpyAsync(base + r->o_pid, r->pid, (size_t)r->n, hipMemcpyHostToDevice, s));
-  // the code check indexes seq[off[k]] with the caller's offsets, so the
-  // bytes are addressed through a base shifted back by the first offset
-  launch_codes(dq - r->q_off[0], dqo, r->n, st, r->qbytes, s);
-  launch_codes(dt - r->t_off[0], dto, r->n, st, r->tbytes, s);
-  SRVCHK(hipGetLastError());
-  SRVCHK(hipMemcpyAsync(r->h_st, st, sizeof(Status), hipMemcpyDeviceToHost, s));
-  SRVCHK(hipEventRecord(r->ready, s));
+  const void* src[6] = {r->q + r->q_off[0], r->t + r->t_off[0], r->q_off, r->t_off, r->h0,
+                        r->pid};
+  const size_t dst[6] = {r->o_q, r->o_t, r->o_qo, r->o_to, r->o_h0, r->o_pid};
+  const size_t len[6] = {r->qbytes, r->tbytes, 8 * (size_t)(r->n + 1),
+                         8 * (size_t)(r->n + 1), 4 * (size_t)r->n,
+                         r->pid ? (size_t)r->n : 0};
+  for (int k = 0; k < 6; ++k) {
+    if (!len[k]) continue;
+    if (r->dsrc[k] && len[k] < GATHER_MAX) {
+      CopySeg& g = segs[(*ns)++];
+      g.src = r->dsrc[k];
+      g.dst = (uint8_t*)base + dst[k];
+      g.bytes = len[k];
+      g.chunk0 = *chunks;
+      *chunks += (len[k] + 4095) / 4096;
+    } else {
+      SRVCHK(hipMemcpyAsync(base + dst[k], src[k], len[k], hipMemcpyHostToDevice, s));
+    }
+  }
   return BSW_OK;
 }
 
 // Grow a slot's buffers for a batch of n pairs from m requests.
 int slot_reserve(Slot& sl, int64_t n, int m) {
   const size_t need = align_up(32 * (size_t)n, 256) + align_up(5 * (size_t)n, 256) +
-                      align_up(40 * (size_t)n, 256) + align_up(sizeof(ReqSlice) * m, 256);
+                      align_up(40 * (size_t)n, 256) + align_up(sizeof(ReqSlice) * m, 256) +
+                      align_up(8 * (size_t)m, 256) + align_up(sizeof(CopySeg) * 6 * m, 256);
   if (need > sl.dev_cap) {
     if (sl.dev) (void)hipFree(sl.dev);
     sl.dev = nullptr;
@@ -224,21 +230,35 @@ int slot_reserve(Slot& sl, int64_t n, int m) {
   }
   if (m > sl.tab_cap) {
     if (sl.h_tab) (void)hipHostFree(sl.h_tab);
+    if (sl.h_seg) (void)hipHostFree(sl.h_seg);
     sl.h_tab = nullptr;
+    sl.h_seg = nullptr;
     sl.tab_cap = 0;
     const int want = std::max(m * 2, 64);
     SRVCHK(hipHostMalloc((void**)&sl.h_tab, sizeof(ReqSlice) * want, 0));
+    SRVCHK(hipHostMalloc((void**)&sl.h_seg, sizeof(CopySeg) * 6 * want, 0));
     sl.tab_cap = want;
   }
-  const size_t res = 40 * (size_t)n;
-  if (res > sl.h_res_cap) {
-    if (sl.h_res) (void)hipHostFree(sl.h_res);
-    sl.h_res = nullptr;
-    sl.h_res_cap = 0;
-    const size_t want = std::max(res + res / 2, (size_t)1 << 20);
-    SRVCHK(hipHostMalloc(&sl.h_res, want, 0));
-    sl.h_res_cap = want;
-  }
+  return BSW_OK;
+}
+
+// A pinned results buffer of at least `bytes` for a slot's next batch: the
+// slot's own, else one from the pool, else a new one (a too-small buffer
+// goes back to the pool; pinned memory is only freed with the server).
+int take_res(bsw_server* v, Slot& sl, size_t bytes) {
+  if (sl.res.p && sl.res.cap >= bytes) return BSW_OK;
+  std::lock_guard<std::mutex> g(v->mu);
+  if (sl.res.p) v->res_pool.push_back(sl.res);
+  sl.res = ResBuf();
+  for (size_t k = 0; k < v->res_pool.size(); ++k)
+    if (v->res_pool[k].cap >= bytes) {
+      sl.res = v->res_pool[k];
+      v->res_pool.erase(v->res_pool.begin() + (long)k);
+      return BSW_OK;
+    }
+  const size_t want = std::max(bytes + bytes / 2, (size_t)1 << 20);
+  SRVCHK(hipHostMalloc(&sl.res.p, want, 0));
+  sl.res.cap = want;
   return BSW_OK;
 }
 
@@ -249,6 +269,8 @@ int launch_batch(bsw_server* v, Slot& sl) {
   for (Req* r : sl.reqs) n += r->n;
   int rc = slot_reserve(sl, n, m);
   if (rc) return rc;
+  // results and diagnostics (40 B per pair), then each request's code flag
+  if ((rc = take_res(v, sl, 40 * (size_t)n + 8 * (size_t)m))) return rc;
   sl.n = n;
   char* d = (char*)sl.dev;
   uint64_t* qb = (uint64_t*)d;
@@ -263,6 +285,19 @@ int launch_batch(bsw_server* v, Slot& sl) {
   bsw_diag* diag = (bsw_diag*)(out + n);
   o += align_up(40 * (size_t)n, 256);
   ReqSlice* tab = (ReqSlice*)(d + o);
+  o += align_up(sizeof(ReqSlice) * m, 256);
+  unsigned long long* bad = (unsigned long long*)(d + o);
+  o += align_up(8 * (size_t)m, 256);
+  CopySeg* segs = (CopySeg*)(d + o);
+  hipStream_t s = sl.s;
+  int ns = 0;
+  unsigned long long chunks = 0;
+  for (Req* r : sl.reqs)
+    if ((rc = upload(v, r, sl.h_seg, &ns, &chunks, s))) return rc;
+  if (ns) {
+    SRVCHK(hipMemcpyAsync(segs, sl.h_seg, sizeof(CopySeg) * ns, hipMemcpyHostToDevice, s));
+    launch_gather(segs, ns, chunks, s);
+  }
   int64_t base = 0;
   for (int k = 0; k < m; ++k) {
     Req* r = sl.reqs[k];
@@ -278,9 +313,12 @@ int launch_batch(bsw_server* v, Slot& sl) {
     e.pid = r->pid ? (const uint8_t*)(rb + r->o_pid) : nullptr;
     base += r->n;
   }
-  hipStream_t s = sl.s;
   SRVCHK(hipMemcpyAsync(tab, sl.h_tab, sizeof(ReqSlice) * m, hipMemcpyHostToDevice, s));
-  launch_assemble(tab, m, n, qb, qe, tb, te, h0, pid, s);
+  // every byte must be a code 0..4; a request with a bad byte is flagged
+  // and gets no bytes in the batch (it fails alone at completion)
+  launch_fill((uint32_t*)bad, 2 * (int64_t)m, s);
+  launch_req_codes(tab, m, n, (const uint8_t*)v->arena_base, bad, s);
+  launch_assemble(tab, m, n, qb, qe, tb, te, h0, pid, bad, s);
   SRVCHK(hipGetLastError());
   const uint8_t* ab = (const uint8_t*)v->arena_base;
   const Args a = {n,  ab,  qb,   ab, tb, h0, pid, (int32_t)v->params.size(),
@@ -289,23 +327,27 @@ int launch_batch(bsw_server* v, Slot& sl) {
   sl.want_diag = false;
   for (Req* r : sl.reqs) sl.want_diag = sl.want_diag || r->diag;
   // results, then diagnostics (contiguous after them) when asked for
-  SRVCHK(hipMemcpyAsync(sl.h_res, out, (sl.want_diag ? 40 : 24) * (size_t)n,
+  SRVCHK(hipMemcpyAsync(sl.res.p, out, (sl.want_diag ? 40 : 24) * (size_t)n,
+                        hipMemcpyDeviceToHost, s));
+  SRVCHK(hipMemcpyAsync((char*)sl.res.p + 40 * (size_t)n, bad, 8 * (size_t)m,
                         hipMemcpyDeviceToHost, s));
   SRVCHK(hipEventRecord(sl.done, s));
   sl.state = SLOT_RUNNING;
   return BSW_OK;
 }
 
-// Mark a request finished (caller holds the lock) and release its region.
-void finish_req(bsw_server* v, Req* r, int rc, Clock::time_point now) {
+// Release a request's device region (caller holds the lock).
+void release_req(bsw_server* v, Req* r) {
+  if (r->bytes) v->arena.release(r->at, r->bytes);
+  r->bytes = 0;
+}
+
+// Mark a request finished (caller holds the lock); its region must already
+// be released.
+void done_req(bsw_server* v, Req* r, int rc, Clock::time_point now) {
   r->rc = rc;
   r->state = DONE;
   r->t_done = now;
-  v->arena.release(r->at, r->bytes);
-  if (r->h_st) v->free_status.push_back(r->h_st);
-  r->h_st = nullptr;
-  if (r->ready) v->free_events.push_back(r->ready);
-  r->ready = nullptr;
   if (rc == BSW_OK) {
     ++v->completed;
     v->pairs += r->n;
@@ -316,35 +358,43 @@ void finish_req(bsw_server* v, Req* r, int rc, Clock::time_point now) {
   v->last_done = now;
 }
 
-// Hand a finished batch's results to its requests.
-void complete_slot(bsw_server* v, Slot& sl) {
-  const int rc = ctx_finish(sl.ctx);
-  const unsigned long long cells = rc == BSW_OK ? ctx_last_cells(sl.ctx) : 0;
-  const bsw_result* res = (const bsw_result*)sl.h_res;
-  const bsw_diag* dg = (const bsw_diag*)(res + sl.n);
+// Both of the above (caller holds the lock).
+void finish_req(bsw_server* v, Req* r, int rc, Clock::time_point now) {
+  release_req(v, r);
+  done_req(v, r, rc, now);
+}
+
+// Hand a finished batch's results to its requests (copier thread).
+void hand_out(bsw_server* v, Handoff& h) {
+  const bsw_result* res = (const bsw_result*)h.buf.p;
+  const bsw_diag* dg = (const bsw_diag*)(res + h.n);
+  const unsigned long long* bad =
+      (const unsigned long long*)((const char*)h.buf.p + 40 * (size_t)h.n);
+  std::vector<int> rc(h.reqs.size(), h.rc);
   int64_t base = 0;
-  for (Req* r : sl.reqs) {
-    if (rc == BSW_OK) {
+  for (size_t k = 0; k < h.reqs.size(); ++k) {
+    Req* r = h.reqs[k];
+    if (h.rc == BSW_OK && bad[k]) {  // a code > 4: the request fails alone
+      rc[k] = BSW_EINVAL;
+      std::snprintf(r->err, sizeof r->err, "pair %llu is invalid (a code > 4)", ~bad[k]);
+    } else if (h.rc == BSW_OK) {
       std::memcpy(r->out, res + base, sizeof(bsw_result) * (size_t)r->n);
       if (r->diag) std::memcpy(r->diag, dg + base, sizeof(bsw_diag) * (size_t)r->n);
+    } else {
+      std::snprintf(r->err, sizeof r->err, "%s", h.err.c_str());
     }
     base += r->n;
   }
   const auto now = Clock::now();
   {
     std::lock_guard<std::mutex> g(v->mu);
-    for (Req* r : sl.reqs) {
-      if (rc != BSW_OK) std::snprintf(r->err, sizeof r->err, "%s", bsw_last_error());
-      finish_req(v, r, rc, now);
-    }
+    for (size_t k = 0; k < h.reqs.size(); ++k) done_req(v, h.reqs[k], rc[k], now);
     ++v->batches;
-    v->batch_pairs_sum += (double)sl.n;
-    v->cells += cells;
+    v->batch_pairs_sum += (double)h.n;
+    v->cells += h.cells;
+    v->res_pool.push_back(h.buf);
   }
   v->cv_done.notify_all();
-  sl.reqs.clear();
-  sl.state = SLOT_FREE;
-  v->cv_work.notify_one();
 }
 
 // Hands finished batches' results to their requests, so that the copies
@@ -352,24 +402,22 @@ void complete_slot(bsw_server* v, Slot& sl) {
 void copier(bsw_server* v) {
   (void)hipSetDevice(v->opts.device);
   for (;;) {
-    int k;
+    Handoff h;
     {
       std::unique_lock<std::mutex> lk(v->mu);
       v->cv_copy.wait(lk, [&] { return !v->copy_q.empty() || v->copier_stop; });
       if (v->copy_q.empty()) return;
-      k = v->copy_q.front();
+      h = std::move(v->copy_q.front());
       v->copy_q.pop_front();
     }
-    complete_slot(v, v->slots[k]);
+    hand_out(v, h);
   }
 }
 
 void scheduler(bsw_server* v) {
   (void)hipSetDevice(v->opts.device);
-  std::vector<Req*> to_upload;
   for (;;) {
     bool progress = false;
-    to_upload.clear();
     {
       std::unique_lock<std::mutex> lk(v->mu);
       // 1. admission, strictly in arrival order
@@ -383,66 +431,50 @@ void scheduler(bsw_server* v) {
         r->t_admit = Clock::now();
         v->admit_wait.push_back(ms_between(r->t_submit, r->t_admit));
         v->admitted.push_back(r);
-        to_upload.push_back(r);
+        progress = true;
       }
       bool busy = false;
       for (auto& sl : v->slots) busy = busy || sl.state != SLOT_FREE;
       if (v->stop && v->pending.empty() && v->admitted.empty() && !busy) break;
-      if (to_upload.empty() && !busy && v->admitted.empty())
+      if (!progress && !busy && v->admitted.empty())
         v->cv_work.wait_for(lk, std::chrono::milliseconds(5));
     }
-    for (Req* r : to_upload) {
-      const int rc = upload(v, r);
-      if (rc) {
+    // 2. completion: a finished batch frees its slot and its requests'
+    //    regions at once; its results (in pinned memory) go to the copier
+    for (auto& sl : v->slots) {
+      if (sl.state != SLOT_RUNNING || hipEventQuery(sl.done) != hipSuccess) continue;
+      Handoff h;
+      h.rc = ctx_finish(sl.ctx);
+      h.cells = h.rc == BSW_OK ? ctx_last_cells(sl.ctx) : 0;
+      if (h.rc != BSW_OK) h.err = bsw_last_error();
+      h.n = sl.n;
+      h.reqs.swap(sl.reqs);
+      h.buf = sl.res;
+      sl.res = ResBuf();
+      {
         std::lock_guard<std::mutex> g(v->mu);
-        std::snprintf(r->err, sizeof r->err, "%s", bsw_last_error());
-        v->admitted.erase(std::find(v->admitted.begin(), v->admitted.end(), r));
-        finish_req(v, r, rc, Clock::now());
-        v->cv_done.notify_all();
+        for (Req* r : h.reqs) release_req(v, r);
+        v->copy_q.push_back(std::move(h));
       }
+      sl.state = SLOT_FREE;
+      v->cv_copy.notify_one();
       progress = true;
     }
-    // 2. completion: finished slots go to the copier
-    for (size_t k = 0; k < v->slots.size(); ++k) {
-      Slot& sl = v->slots[k];
-      if (sl.state == SLOT_RUNNING && hipEventQuery(sl.done) == hipSuccess) {
-        sl.state = SLOT_COPYING;
-        {
-          std::lock_guard<std::mutex> g(v->mu);
-          v->copy_q.push_back((int)k);
-        }
-        v->cv_copy.notify_one();
-        progress = true;
-      }
-    }
-    // 3. dispatch: a free slot takes every ready admitted request
+    // 3. dispatch: a free slot takes the admitted requests in order, up to
+    //    max_batch_pairs (a larger request runs alone)
     for (auto& sl : v->slots) {
       if (sl.state != SLOT_FREE) continue;
       std::vector<Req*> batch;
       {
         std::lock_guard<std::mutex> g(v->mu);
         int64_t n = 0;
-        for (auto it = v->admitted.begin(); it != v->admitted.end();) {
-          Req* r = *it;
-          if (hipEventQuery(r->ready) != hipSuccess) {
-            ++it;
-            continue;
-          }
-          if (r->h_st->bad) {  // a code > 4: the request fails alone
-            std::snprintf(r->err, sizeof r->err,
-                          "pair %llu is invalid (a code > 4)",
-                          ~(unsigned long long)r->h_st->first_bad_inv);
-            it = v->admitted.erase(it);
-            finish_req(v, r, BSW_EINVAL, Clock::now());
-            v->cv_done.notify_all();
-            progress = true;
-            continue;
-          }
+        while (!v->admitted.empty()) {
+          Req* r = v->admitted.front();
           if (!batch.empty() && n + r->n > v->opts.max_batch_pairs) break;
           n += r->n;
           r->state = RUNNING;
           batch.push_back(r);
-          it = v->admitted.erase(it);
+          v->admitted.pop_front();
         }
       }
       if (batch.empty()) break;
@@ -479,15 +511,12 @@ void destroy_server(bsw_server* v) {
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.dev) (void)hipFree(sl.dev);
     if (sl.h_tab) (void)hipHostFree(sl.h_tab);
-    if (sl.h_res) (void)hipHostFree(sl.h_res);
+    if (sl.h_seg) (void)hipHostFree(sl.h_seg);
+    if (sl.res.p) (void)hipHostFree(sl.res.p);
     if (sl.ctx) bsw_ctx_destroy(sl.ctx);
   }
-  if (v->up) {
-    (void)hipStreamSynchronize(v->up);
-    (void)hipStreamDestroy(v->up);
-  }
-  for (auto e : v->free_events) (void)hipEventDestroy(e);
-  for (auto b : v->status_blocks) (void)hipHostFree(b);
+  for (auto& b : v->res_pool) (void)hipHostFree(b.p);
+  for (auto& h : v->copy_q) (void)hipHostFree(h.buf.p);
   if (v->arena_base) (void)hipFree(v->arena_base);
   for (auto& kv : v->by_ticket) delete kv.second;
   delete v;
@@ -503,13 +532,13 @@ int bsw_server_create(bsw_server** out, const bsw_server_opts* opts,
   bsw_server_opts o;
   std::memset(&o, 0, sizeof o);
   if (opts) o = *opts;
-  if (o.max_inflight == 0) o.max_inflight = 2;
+  if (o.max_inflight == 0) o.max_inflight = 3;
   if (o.max_inflight < 1 || o.max_inflight > 8)
     return set_error(BSW_EINVAL, "max_inflight must be 1..8");
   if (o.max_batch_pairs == 0) o.max_batch_pairs = (int64_t)1 << 22;
   if (o.max_batch_pairs < 1 || o.max_batch_pairs > 0x7fffffffLL)
     return set_error(BSW_EINVAL, "max_batch_pairs out of range");
-  if (o.hbm_budget == 0) o.hbm_budget = (size_t)8 << 30;
+  if (o.hbm_budget == 0) o.hbm_budget = (size_t)16 << 30;
   if (o.max_queued == 0) o.max_queued = 65536;
   if (o.max_queued < 1) return set_error(BSW_EINVAL, "max_queued must be >= 1");
   bsw_server* v = new (std::nothrow) bsw_server;
@@ -526,6 +555,10 @@ int bsw_server_create(bsw_server** out, const bsw_server_opts* opts,
   for (auto& sl : v->slots) {
     if ((rc = bsw_ctx_create(&sl.ctx, &co))) break;
     if ((rc = ctx_set_params(sl.ctx, params, n_params))) break;
+    // a slot runs its classes in order on its own stream: with one stream
+    // per slot the slots hold separate hardware queues, so one slot's
+    // uploads and kernels never wait behind the other's
+    ctx_set_side_streams(sl.ctx, 0);
     // workspaces for a full batch up front: growing them later would free
     // device memory, which waits for all work on the device
     if ((rc = ctx_reserve(sl.ctx, o.max_batch_pairs, n_params))) break;
@@ -536,11 +569,21 @@ int bsw_server_create(bsw_server** out, const bsw_server_opts* opts,
       break;
     }
   }
+  // pinned results buffers for a full batch: one per slot and a spare, so
+  // that a slot can start its next batch while the copier still hands out
+  // the last one
+  for (auto& sl : v->slots) {
+    if (rc != BSW_OK) break;
+    rc = take_res(v, sl, 40 * (size_t)o.max_batch_pairs);
+  }
+  if (rc == BSW_OK) {
+    Slot spare;
+    if ((rc = take_res(v, spare, 40 * (size_t)o.max_batch_pairs)) == BSW_OK)
+      v->res_pool.push_back(spare.res);
+  }
   if (rc == BSW_OK) {
     v->params.assign(params, params + n_params);
-    if (hipStreamCreateWithFlags(&v->up, hipStreamNonBlocking) != hipSuccess)
-      rc = set_error(BSW_EDEVICE, "stream creation failed");
-    else if (hipMalloc((void**)&v->arena_base, o.hbm_budget) != hipSuccess) {
+    if (hipMalloc((void**)&v->arena_base, o.hbm_budget) != hipSuccess) {
       v->arena_base = nullptr;
       rc = set_error(BSW_ENOMEM, "arena of %zu bytes does not fit", o.hbm_budget);
     }
@@ -607,6 +650,10 @@ int bsw_server_submit(bsw_server* v, int64_t n, const uint8_t* q, const uint64_t
   r->diag = diag;
   r->qbytes = q_off[n] - q_off[0];
   r->tbytes = t_off[n] - t_off[0];
+  {
+    const void* src[6] = {q + q_off[0], t + t_off[0], q_off, t_off, h0, param_id};
+    for (int k = 0; k < 6; ++k) r->dsrc[k] = src[k] ? device_view(src[k]) : nullptr;
+  }
   plan_region(r);
   if (r->bytes > v->arena.size()) {
     const size_t b = r->bytes;

@@ -169,3 +169,53 @@ def test_bad_request_fails_alone(bsw, pool):
                 _same(srv.wait(tk), want[a:a + s], f"request {k}")
         st = srv.stats()
         assert st["failed"] == 1 and st["completed"] == 5
+
+
+def _pinned(a):
+    """A copy of a host array in pinned (page-locked) memory."""
+    import torch
+    a = np.ascontiguousarray(a)
+    buf = torch.empty(max(a.nbytes, 1), dtype=torch.uint8, pin_memory=True)
+    out = buf.numpy()[:a.nbytes].view(a.dtype).reshape(a.shape)
+    out[...] = a
+    return out, buf
+
+
+def test_pinned_requests_read_by_the_device(bsw, pool):
+    # requests whose arrays are in pinned memory are gathered by the device
+    # itself; mixed in one batch with requests in pageable memory, and one
+    # pinned request with a bad code, which fails alone
+    b, want, wdiag = pool
+    keep = []
+    pq, bq = _pinned(b["q"])
+    pt, bt = _pinned(b["t"])
+    pqo, bqo = _pinned(b["q_off"])
+    pto, bto = _pinned(b["t_off"])
+    ph0, bh0 = _pinned(b["h0"])
+    keep += [bq, bt, bqo, bto, bh0]
+    bad_t, bbt = _pinned(b["t"])
+    keep.append(bbt)
+    reqs = slices(b, synth.serving_requests(n_requests=30, seed=53, lo=300, hi=9_000))
+    sent = []
+    for k, (a, s, r) in enumerate(reqs):
+        if k % 3 != 2:  # two of three requests in pinned memory
+            r = {"q": pq, "t": pt, "q_off": pqo[a:a + s + 1], "t_off": pto[a:a + s + 1],
+                 "h0": ph0[a:a + s], "scorings": b["scorings"]}
+        sent.append((a, s, r))
+    a7, s7, r7 = sent[7]
+    bad_t[int(b["t_off"][a7 + 5]) + 1] = 9
+    sent[7] = (a7, s7, dict(r7, t=bad_t))
+    with bsw.Server(b["scorings"], max_inflight=2) as srv:
+        tks = [(a, s, srv.submit(r, with_diag=True)) for a, s, r in sent]
+        for k, (a, s, tk) in enumerate(tks):
+            if k == 7:
+                with pytest.raises(bsw.BswError) as ei:
+                    srv.wait(tk)
+                assert ei.value.code == bsw.EINVAL and "5" in str(ei.value)
+                continue
+            got, gd = srv.wait(tk)
+            _same(got, want[a:a + s], f"request {k} at {a}")
+            assert np.array_equal(gd["cells"], wdiag["cells"][a:a + s])
+        st = srv.stats()
+    assert st["failed"] == 1 and st["completed"] == len(sent) - 1
+    del keep
