@@ -82,16 +82,6 @@ struct ReqSlice {
   const uint8_t* pid;        // its n scoring-set indices (device) or null
 };
 
-// One byte range a serving batch copies from host memory the device can
-// read (pinned, mapped) into its arena (see k_gather); chunk0 is the first
-// 4 KiB chunk of the range in the batch's list of chunks.
-struct CopySeg {
-  const uint8_t* src;
-  uint8_t* dst;
-  unsigned long long bytes;
-  unsigned long long chunk0;
-};
-
 // Launch records name a wave-mode launch of a 32-bit class as the class
 // plus WAVE_TAG (its cells are counted under the class).
 constexpr int WAVE_TAG = 32;

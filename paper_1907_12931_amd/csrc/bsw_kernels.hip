@@ -28,6 +28,7 @@
 #include "bsw_device.h"
 #include "bsw_internal.h"
 #include "bsw_lanev.h"
+#include "bsw_runtime.h"
 
 namespace bsw {
 

@@ -145,6 +145,16 @@ void fm_state_free(FmState* s);
 void launch_fill(uint32_t* p, int64_t nwords, hipStream_t s);
 void launch_codes(const uint8_t* seq, const uint64_t* off, int64_t n, Status* st,
                   uint64_t bytes, hipStream_t s);
+// One byte range a serving batch copies from host memory the device can
+// read (pinned, mapped) into its arena (see k_gather); chunk0 is the first
+// 4 KiB chunk of the range in the batch's list of chunks.
+struct CopySeg {
+  const uint8_t* src;
+  uint8_t* dst;
+  unsigned long long bytes;
+  unsigned long long chunk0;
+};
+
 // Copy the byte ranges segs[0 .. ns) (nchunks 4 KiB chunks in all) from
 // mapped host memory to the device.
 void launch_gather(const CopySeg* segs, int ns, unsigned long long nchunks, hipStream_t s);
