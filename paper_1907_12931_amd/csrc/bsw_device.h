@@ -71,7 +71,9 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 // into rows 2 and 3.  Every lane must be active.
 template <bool MAX>
 __device__ __forceinline__ int wave_scan(int x) {
-  constexpr int ID = MAX ? -(1 << 30) : 0;
+  // the identity of the operation, so that the compiler folds each DPP
+  // move into its max or add
+  constexpr int ID = MAX ? (int)0x80000000u : 0;
   auto op = [](int a, int b) { return MAX ? (a > b ? a : b) : a + b; };
   x = op(x, __builtin_amdgcn_update_dpp(ID, x, 0x111, 0xf, 0xf, false));  // row_shr:1
   x = op(x, __builtin_amdgcn_update_dpp(ID, x, 0x112, 0xf, 0xf, false));  // row_shr:2
@@ -89,19 +91,23 @@ __device__ __forceinline__ int wave_prefix_max(int x) { return wave_scan<true>(x
 // pairs, half-row mirror, row mirror), then the four row results are read
 // out and combined on the scalar unit.  Every lane must be active.
 __device__ __forceinline__ int wave_min(int v) {
-  v = imin(v, __builtin_amdgcn_update_dpp(v, v, 0xb1, 0xf, 0xf, false));
-  v = imin(v, __builtin_amdgcn_update_dpp(v, v, 0x4e, 0xf, 0xf, false));
-  v = imin(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));
-  v = imin(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));
+  // every lane has a source in these patterns; the identity as the old
+  // value lets the compiler fold each DPP move into its min
+  constexpr int ID = 0x7fffffff;
+  v = imin(v, __builtin_amdgcn_update_dpp(ID, v, 0xb1, 0xf, 0xf, false));
+  v = imin(v, __builtin_amdgcn_update_dpp(ID, v, 0x4e, 0xf, 0xf, false));
+  v = imin(v, __builtin_amdgcn_update_dpp(ID, v, 0x141, 0xf, 0xf, false));
+  v = imin(v, __builtin_amdgcn_update_dpp(ID, v, 0x140, 0xf, 0xf, false));
   const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
   const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
   return imin(imin(a, b), imin(c, d));
 }
 __device__ __forceinline__ int wave_max(int v) {
-  v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0xb1, 0xf, 0xf, false));
-  v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x4e, 0xf, 0xf, false));
-  v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));
-  v = imax(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));
+  constexpr int ID = (int)0x80000000u;
+  v = imax(v, __builtin_amdgcn_update_dpp(ID, v, 0xb1, 0xf, 0xf, false));
+  v = imax(v, __builtin_amdgcn_update_dpp(ID, v, 0x4e, 0xf, 0xf, false));
+  v = imax(v, __builtin_amdgcn_update_dpp(ID, v, 0x141, 0xf, 0xf, false));
+  v = imax(v, __builtin_amdgcn_update_dpp(ID, v, 0x140, 0xf, 0xf, false));
   const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
   const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
   return imax(imax(a, b), imax(c, d));

@@ -1096,8 +1096,11 @@ constexpr int WAVE_CAP = 256;  // longest query of the wave kernel
 constexpr int NEG = -(1 << 30);
 
 __device__ __forceinline__ int wave_prefix_max_excl(int x) {
-  // shift the inclusive scan one lane up across the whole wave
-  return __builtin_amdgcn_update_dpp(NEG, wave_scan<true>(x), 0x138, 0xf, 0xf, false);
+  // shift the inclusive scan one lane up across the whole wave; lane 0 and
+  // lanes after NEG-only prefixes read NEG
+  return imax(__builtin_amdgcn_update_dpp((int)0x80000000u, wave_scan<true>(x), 0x138, 0xf,
+                                          0xf, false),
+              NEG);
 }
 
 __global__ void __launch_bounds__(64)
@@ -1313,9 +1316,11 @@ k_wavev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
       // edge when the band is empty)
       const int s0 = imin(beg, end) >> 6, s1 = end >> 6;
       span += (unsigned)(imin(s1, NSEG - 1) + 1 - imin(s0, NSEG));
+      // the steps s0 .. s1 as a bit mask (one scalar test per step)
+      const uint32_t steps = (s1 >= 31 ? ~0u : ((2u << s1) - 1u)) & (~0u << imin(s0, 31));
 #pragma unroll
       for (int sg = 0; sg < NSEG; ++sg) {
-        if (sg < s0 || sg > s1) continue;
+        if (!(steps & (1u << sg))) continue;
         const int jb = 64 * sg, j = jb + lane;
         const bool in = j >= beg && j < end;
         const int d = hd[sg], e = ev[sg];
