@@ -1318,11 +1318,13 @@ k_wavev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
       span += (unsigned)(imin(s1, NSEG - 1) + 1 - imin(s0, NSEG));
       // the steps s0 .. s1 as a bit mask (one scalar test per step)
       const uint32_t steps = (s1 >= 31 ? ~0u : ((2u << s1) - 1u)) & (~0u << imin(s0, 31));
+      // j in [beg, end) as one unsigned compare
+      const uint32_t blen = (uint32_t)imax(end - beg, 0);
 #pragma unroll
       for (int sg = 0; sg < NSEG; ++sg) {
         if (!(steps & (1u << sg))) continue;
         const int jb = 64 * sg, j = jb + lane;
-        const bool in = j >= beg && j < end;
+        const bool in = (uint32_t)(j - beg) < blen;
         const int d = hd[sg], e = ev[sg];
         const int sc = score_of(lo, hi, qc[sg]);
         const int M = d > 0 ? d + sc : 0;
@@ -1337,10 +1339,14 @@ k_wavev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         // the band's first column and the right edge of an empty band take
         // the row's left boundary H(i, beg - 1)
         if (j == (beg < end ? beg : end)) hp = hl;
-        if (in || j == end) {
-          hd[sg] = hp;
-          ev[sg] = in ? imax(imax(e - eD, M - oeD), 0) : 0;
-        }
+        // stored: the band's columns and the right edge, by selects (the
+        // empty asm keeps the new E from being sunk into a branch, whose
+        // exec-mask bookkeeping would load the scalar unit)
+        int en = imax(imax(e - eD, M - oeD), 0);
+        asm volatile("" : "+v"(en));
+        const bool st_col = in || j == end;
+        hd[sg] = st_col ? hp : d;
+        ev[sg] = st_col ? (in ? en : 0) : e;
         if (in && h >= lh) {
           lh = h;
           lj = j;
@@ -1386,24 +1392,25 @@ k_wavev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
         }
       }
       // shrink the band by its empty ends (Sec. 5.1 (c)): the first
-      // non-empty index in [beg, end), the last one in [beg, end]
-      int nb = end;
+      // non-empty index in [beg, end) (else end), the last one in [beg,
+      // end] (else beg - 1); each lane takes its own columns first, then
+      // one wave reduction (vector work rather than a chain of scalar
+      // tests, which the scalar unit of a busy CU cannot keep up with)
+      int jlo = 0x7fffffff;
+#pragma unroll
+      for (int sg = NSEG - 1; sg >= 0; --sg) {
+        const int j = lane + 64 * sg;
+        if ((uint32_t)(j - beg) < blen && (hd[sg] | ev[sg]) != 0) jlo = j;
+      }
+      const int nb = imin(wave_min(jlo), end);
+      int jhi = -1;
 #pragma unroll
       for (int sg = 0; sg < NSEG; ++sg) {
         const int j = lane + 64 * sg;
-        const unsigned long long mk =
-            __ballot(j >= beg && j < end && (hd[sg] | ev[sg]) != 0);
-        if (nb == end && mk) nb = 64 * sg + __builtin_ctzll(mk);
+        if ((uint32_t)(j - nb) <= (uint32_t)(end - nb) && (hd[sg] | ev[sg]) != 0) jhi = j;
       }
-      int x = nb - 1;
+      int x = imax(wave_max(jhi), nb - 1);
       if (end == CAPW && hcap != 0) x = CAPW;
-#pragma unroll
-      for (int sg = 0; sg < NSEG; ++sg) {
-        const int j = lane + 64 * sg;
-        const unsigned long long mk =
-            __ballot(j >= nb && j <= end && (hd[sg] | ev[sg]) != 0);
-        if (mk) x = imax(x, 64 * sg + 63 - __builtin_clzll(mk));
-      }
       beg = nb;
       end = imin(x + 2, Lq);
     }
