@@ -45,32 +45,97 @@ __global__ void k_fill(uint32_t* p, int64_t nwords) {
 }
 
 
-// Estimated rows of a pair for the sort key: walk the main diagonal without
-// gaps from h0 until the running score falls to zero or more than z-drop
-// below its running maximum (Sec. 5.1 (b)); the whole wave walks one pair,
-// 64 positions per step.  Only the order of the pairs depends on it.
-// Returns the stopping row + 1, or INT_MAX if the walk reaches its end.
-__device__ int diagonal_rows(const uint8_t* qs, const uint8_t* ts, int L, int h0,
-                             const KParams& P) {
+// Estimated rows of a pair for the sort key (only the order of the pairs
+// depends on it).  The whole wave walks one pair, 64 positions per step:
+// along a diagonal without gaps from h0, the running score is followed
+// until it falls to zero or more than z-drop below its running maximum
+// (the stops of Sec. 5.1 (b)).
+//  - a stop at zero says little (the band still holds other diagonals, and
+//    the extension seldom ends there): the estimate is `cap`;
+//  - a z-drop is often an indel rather than the end of the alignment: the
+//    sequences are compared again after the best position on the diagonals
+//    +-1 .. +-ESTIMATE_SHIFT (32 positions, at least 5 in 8 equal); where
+//    they agree the walk goes on there from the best score less the gap's
+//    cost, otherwise the stop row is the estimate;
+//  - a walk that reaches the end of either sequence gives `cap`.
+// qs/ts hold Lq/Lt codes; cap = the last row any cell can have + 1.
+constexpr int ESTIMATE_SHIFT = 8;
+constexpr int ESTIMATE_HOPS = 8;
+
+__device__ int estimate_rows(const uint8_t* qs, const uint8_t* ts, int Lq, int Lt, int h0,
+                             const KParams& P, int cap) {
   const int lane = threadIdx.x & 63;
-  int base = h0, mx = h0;
-  for (int j0 = 0; j0 < L; j0 += 64) {
-    const int j = j0 + lane;
-    int sc = 0;
-    if (j < L) {
-      const int a = ts[j], bq = qs[j];
-      sc = (int)(int8_t)(__builtin_amdgcn_perm(P.prow[a < 5 ? a : 0][1],
-                                               P.prow[a < 5 ? a : 0][0], bq) & 0xffu);
+  int pq = 0, pt = 0;      // start of the diagonal being walked
+  int base = h0, mx = h0;  // score entering it, best score so far
+  for (int hop = 0; hop < ESTIMATE_HOPS; ++hop) {
+    const int L = imin(Lq - pq, Lt - pt);
+    int bpos = -1;  // position of the best score on this diagonal (-1: its start)
+    int stop = -1;  // position of the z-drop
+    for (int j0 = 0; j0 < L; j0 += 64) {
+      const int j = j0 + lane;
+      int sc = 0;
+      if (j < L) {
+        const int a = ts[pt + j], bq = qs[pq + j];
+        sc = (int)(int8_t)(__builtin_amdgcn_perm(P.prow[a < 5 ? a : 0][1],
+                                                 P.prow[a < 5 ? a : 0][0], bq) & 0xffu);
+      }
+      const int run = base + wave_prefix_sum(sc);
+      const int rmx = imax(mx, wave_prefix_max(run));
+      const bool zs = j < L && P.zdrop > 0 && rmx - run > P.zdrop;
+      const unsigned long long m = __ballot(j < L && (run <= 0 || zs));
+      const int last = m ? __builtin_ctzll(m) : 63;  // lanes up to the stop count
+      const int rlast = __shfl(rmx, last, 64);
+      if (rlast > mx) {
+        const unsigned long long at = __ballot(lane <= last && j < L && run == rlast);
+        bpos = j0 + __builtin_ctzll(at);
+        mx = rlast;
+      }
+      if (m) {
+        if (!__shfl((int)zs, last, 64)) return cap;
+        stop = j0 + last;
+        break;
+      }
+      base = __shfl(run, 63, 64);
     }
-    const int run = base + wave_prefix_sum(sc);
-    const int rmx = imax(mx, wave_prefix_max(run));
-    const bool stop = j < L && (run <= 0 || (P.zdrop > 0 && rmx - run > P.zdrop));
-    const unsigned long long m = __ballot(stop);
-    if (m) return j0 + __builtin_ctzll(m) + 1;
-    base = __shfl(run, 63, 64);
-    mx = __shfl(rmx, 63, 64);
+    if (stop < 0) return cap;
+    // look for the sequences to agree again after the best position: lanes
+    // 0-31 try the shift +d (extra target bases: target read d further on),
+    // lanes 32-63 the shift -d (extra query bases); every byte is loaded
+    // before the first comparison
+    const int aq = pq + bpos + 1, at = pt + bpos + 1, x = lane & 31;
+    const bool up = lane < 32;
+    const uint8_t* fs = up ? qs + aq : ts + at;  // the side read unshifted
+    const uint8_t* ss = up ? ts + at : qs + aq;  // the side read at +d
+    const int flen = up ? Lq - aq : Lt - at, slen = up ? Lt - at : Lq - aq;
+    const uint32_t f = x < flen ? fs[x] : 4u;
+    uint32_t sv[ESTIMATE_SHIFT];
+#pragma unroll
+    for (int d = 1; d <= ESTIMATE_SHIFT; ++d) sv[d - 1] = x + d < slen ? ss[x + d] : 5u;
+    int nq = -1, nt = -1, dd = 0;
+#pragma unroll
+    for (int d = 1; d <= ESTIMATE_SHIFT; ++d) {
+      const int n = imin(32, imin(flen, slen - d));
+      const unsigned long long e = __ballot(x < n && f < 4 && f == sv[d - 1]);
+      const int n_lo = __shfl(n, 0, 64), n_hi = __shfl(n, 32, 64);
+      const int c_lo = __builtin_popcount((uint32_t)e);
+      const int c_hi = __builtin_popcount((uint32_t)(e >> 32));
+      if (nq < 0 && n_lo >= 8 && 8 * c_lo >= 5 * n_lo) {
+        nq = aq;
+        nt = at + d;
+        dd = d;
+      } else if (nq < 0 && n_hi >= 8 && 8 * c_hi >= 5 * n_hi) {
+        nq = aq + d;
+        nt = at;
+        dd = d;
+      }
+    }
+    if (nq < 0) return imin(pt + stop + 1, cap);
+    base = mx - P.o_del - dd * P.e_del;
+    if (base <= 0) return cap;
+    pq = nq;
+    pt = nt;
   }
-  return 0x7fffffff;  // the walk never stops: no estimate
+  return cap;
 }
 
 // Add one to cnt[key] for every lane with active set, with one atomic per
@@ -148,10 +213,11 @@ k_prep(int64_t n, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
       const int l = __builtin_ctzll(walk);
       walk &= walk - 1;
       const uint64_t wq = __shfl(qo, l, 64), wt = __shfl(to, l, 64);
-      const int wl = imin(__shfl(ql, l, 64), __shfl(tl, l, 64));
+      const int wlq = __shfl(ql, l, 64), wlt = __shfl(tl, l, 64);
       const int wh = __shfl(hh, l, 64), wp = __shfl(p, l, 64);
-      const int r = diagonal_rows(q + wq, t + wt, wl, wh, kp[wp]);
-      if (lane == l) rows_est = imin(rows_est, r);
+      const int wcap = __shfl(rows_est, l, 64);
+      const int r = estimate_rows(q + wq, t + wt, wlq, wlt, wh, kp[wp], wcap);
+      if (lane == l) rows_est = r;
     }
     uint32_t key = 0;
     if (ok) {
@@ -181,7 +247,7 @@ k_prep(int64_t n, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
         cap = LW_CAP[c];
       }
       int qq = (int)((int64_t)ql * 64 / (cap + 1));
-      int tq = rows_est >> 4;
+      int tq = rows_est >> 3;
       qq = qq > 63 ? 63 : qq;
       tq = tq > 63 ? 63 : (tq < 0 ? 0 : tq);
       const uint32_t sub = ((uint32_t)(63 - qq) << 6) | (uint32_t)(63 - tq);
