@@ -769,8 +769,14 @@ def bsw_paths(bsw, torch, np, batch, steps, warmup, tune_cache, tune=True, batch
             dp_ms.append(tm[2])
             prep_ms.append(tm[1])
             launches = int(tm[3])
+            # a name can have several launches in a call (the reruns that
+            # follow each lane class): summed per call
+            step = {}
             for (name, kc, kms), kw in zip(ctx.last_kernels(), ctx.last_work()):
-                per_kernel.setdefault(name, []).append((kc, kms, kw))
+                c0, m0, w0 = step.get(name, (0, 0.0, 0))
+                step[name] = (c0 + kc, m0 + kms, w0 + kw)
+            for name, v in step.items():
+                per_kernel.setdefault(name, []).append(v)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t) / steps
         ctx.close()

@@ -603,6 +603,7 @@ k_lane(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
   uint8_t* qb = smem + wv * PER_WAVE + HB_BYTES + lane;
   const long long begin = range[0], count = range[1];
   const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
+  if (ntiles == 0) return;  // an empty class: no atomics
   uint32_t tile = blockIdx.x * (blockDim.x >> 6) + wv;
   unsigned long long acc = 0;
   for (;;) {
@@ -842,6 +843,7 @@ k_lanec(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
 #define COL(x) (*(R*)(myb + ring_slot((x) >> 2, RC) * (64 * CK::BYTES) + ((x) & 3) * CK::REC))
   const long long begin = range[0], count = range[1];
   const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
+  if (ntiles == 0) return;  // an empty class: no atomics
   uint32_t tile = blockIdx.x;
   unsigned long long tile_cells_acc = 0;
   unsigned long long span_chunks = 0;  // chunks stepped, summed over rows
@@ -1179,6 +1181,7 @@ k_wave(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
   __shared__ int2 hb[WAVE_CAP + 1];
   const int lane = threadIdx.x;
   const long long begin = range[0], count = range[1];
+  if (count <= 0) return;  // an empty list: no atomics
   unsigned long long acc = 0;
   for (;;) {
     uint32_t v0 = 0;
@@ -1337,6 +1340,7 @@ k_wavev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
   constexpr int CAPW = 64 * NSEG;
   const int lane = threadIdx.x;
   const long long begin = range[0], count = range[1];
+  if (count <= 0) return;  // an empty list: no atomics
   unsigned long long acc = 0, span = 0;
   for (;;) {
     uint32_t v0 = 0;
@@ -1514,6 +1518,7 @@ k_long(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
        unsigned long long* __restrict__ cls_cells) {
   if (st->bad) return;
   const long long begin = range[0], count = range[1];
+  if (count <= 0) return;  // an empty list: no atomics
   int2* hb = gbuf + (size_t)blockIdx.x * LONG_SLOT_COLS;
   uint8_t* qb = gq + (size_t)blockIdx.x * LONG_SLOT_COLS;
   for (;;) {

@@ -217,6 +217,7 @@ k_lanev(const PairDesc* __restrict__ desc, const long long* __restrict__ range,
 #define MIRW(x) mir[((x) >> 2) * 64]
   const long long begin = range[0], count = range[1];
   const uint32_t ntiles = (uint32_t)((count + 63) >> 6);
+  if (ntiles == 0) return;  // an empty class: no atomics
   uint32_t tile = blockIdx.x;
   // settled cells and lane-cells stepped through, summed over the wave's
   // tiles (wave-uniform, so that they take no vector registers)
