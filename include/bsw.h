@@ -193,7 +193,9 @@ int bsw_extend_batch_device_noalloc(bsw_ctx* ctx, int64_t n,
  * a normal call) under candidate launch shapes, by coordinate descent from
  * the default shape: each knob in turn takes every value while the others
  * stay at the best so far.  The knobs are the side streams the kernel
- * classes are spread over (4, 2, 1), the share of resident groups per CU
+ * classes are spread over (4, 2, 1; at most GPU_MAX_HW_QUEUES - 2, so that
+ * with the caller's and the runtime's default stream no two streams share a
+ * hardware queue; default 2), the share of resident groups per CU
  * for the 8-bit classes (100%, 75%, 50%), whether pairs whose score bound
  * needs 16 bits are tried at 8 bits first (yes, no), and the query cap from
  * which the 32-bit classes run one pair per wave instead of one pair per

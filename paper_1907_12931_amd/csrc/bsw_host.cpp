@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -652,11 +653,21 @@ int tune_shapes(bsw_ctx* c, int kind, int n_params, int reps, int (*run)(bsw_ctx
     std::sort(ts.begin(), ts.end());
     *med = ts[ts.size() / 2];
   };
-  Tune best;
-  double best_t = 1e300;
-  score(best, &best_t);
   static const int nsides[] = {4, 2, 1}, occs[] = {100, 75, 50}, specs[] = {1, 0},
                    waves[] = {64, 128, 256, 512, 32};
+  // more streams than hardware queues share queues: a side stream then
+  // waits behind another stream's work (the graph replay of such a shape
+  // lost about 1 ms against two side streams, where eager timing showed
+  // no loss), so the tuner keeps the caller's stream, the runtime's default
+  // stream and the side streams within the queues the process has
+  // (GPU_MAX_HW_QUEUES, 4 unless set)
+  const char* hwq_env = std::getenv("GPU_MAX_HW_QUEUES");
+  const int hwq = hwq_env && std::atoi(hwq_env) > 0 ? std::atoi(hwq_env) : 4;
+  const int nside_max = std::max(1, std::min(bsw_ctx::NSIDE, hwq - 2));
+  Tune best;
+  best.nside = std::min(best.nside, nside_max);
+  double best_t = 1e300;
+  score(best, &best_t);
   for (int knob = 0; knob < 4 && rc == BSW_OK; ++knob) {
     const int* vals = knob == 0 ? nsides : knob == 1 ? occs : knob == 2 ? specs : waves;
     const int nv = knob == 0 ? 3 : knob == 1 ? 3 : knob == 2 ? 2 : 5;
@@ -664,7 +675,7 @@ int tune_shapes(bsw_ctx* c, int kind, int n_params, int reps, int (*run)(bsw_ctx
     for (int v = 0; v < nv && rc == BSW_OK; ++v) {
       Tune x = base;
       int& field = knob == 0 ? x.nside : knob == 1 ? x.occ8 : knob == 2 ? x.spec16 : x.wave32;
-      if (field == vals[v]) continue;
+      if (field == vals[v] || (knob == 0 && vals[v] > nside_max)) continue;
       field = vals[v];
       double med = 0;
       score(x, &med);

@@ -71,7 +71,10 @@ class Arena {
 
 // Launch shapes of the batched path that the tuner chooses.
 struct Tune {
-  int nside = 4;    // side streams the classes are spread over (1..4)
+  int nside = 2;    // side streams the classes are spread over (1..4); two
+                    // keep the caller's stream, the runtime's default
+                    // stream and the side streams within the four
+                    // hardware queues a process gets by default
   int occ8 = 100;   // percent of the resident groups per CU for 8-bit classes
   int spec16 = 1;   // try pairs whose bound needs 16 bits at 8 bits first
   int wave32 = 64;  // 32-bit classes with a query cap >= this run one pair
