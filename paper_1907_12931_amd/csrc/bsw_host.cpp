@@ -467,7 +467,12 @@ int enqueue_batched(bsw_ctx* c, const Args& a, const Work& w, const BatchedPlan&
   for (int cls = CLS_W16; cls < CLS_LONG; ++cls) order[no++] = cls;
   for (int oi = 0; oi < no; ++oi) {
     const int cls = order[oi];
-    hipStream_t ls = nside > 0 ? c->side[oi % nside] : s;
+    // with 16-bit pairs tried at 8 bits first, the 16-bit classes hold only
+    // the few pairs that cannot start there: they run on the call's own
+    // stream, idle until the join, beside the 8-bit classes
+    const bool beside = nside > 0 && c->tunes[c->kind].spec16 && cls >= CLS_W16 &&
+                        cls < CLS_W32;
+    hipStream_t ls = nside > 0 && !beside ? c->side[oi % nside] : s;
     if ((rc = begin_launch(c, cls | (wave_mode(c, cls) ? WAVE_TAG : 0), ls))) return rc;
     // pairs a narrow class cannot settle in its record width go to the
     // rerun list

@@ -58,12 +58,13 @@ __global__ void k_fill(uint32_t* p, int64_t nwords) {
 //    they agree the walk goes on there from the best score less the gap's
 //    cost, otherwise the stop row is the estimate;
 //  - a walk that reaches the end of either sequence gives `cap`.
-// qs/ts hold Lq/Lt codes; cap = the last row any cell can have + 1.
+// qs/ts hold Lq/Lt codes; cap = the last row any cell can have + 1.  best
+// receives the walk's best score: a path the extension scores as well.
 constexpr int ESTIMATE_SHIFT = 8;
 constexpr int ESTIMATE_HOPS = 8;
 
 __device__ int estimate_rows(const uint8_t* qs, const uint8_t* ts, int Lq, int Lt, int h0,
-                             const KParams& P, int cap) {
+                             const KParams& P, int cap, int& best) {
   const int lane = threadIdx.x & 63;
   int pq = 0, pt = 0;      // start of the diagonal being walked
   int base = h0, mx = h0;  // score entering it, best score so far
@@ -91,13 +92,19 @@ __device__ int estimate_rows(const uint8_t* qs, const uint8_t* ts, int Lq, int L
         mx = rlast;
       }
       if (m) {
-        if (!__shfl((int)zs, last, 64)) return cap;
+        if (!__shfl((int)zs, last, 64)) {
+          best = mx;
+          return cap;
+        }
         stop = j0 + last;
         break;
       }
       base = __shfl(run, 63, 64);
     }
-    if (stop < 0) return cap;
+    if (stop < 0) {
+      best = mx;
+      return cap;
+    }
     // look for the sequences to agree again after the best position: lanes
     // 0-31 try the shift +d (extra target bases: target read d further on),
     // lanes 32-63 the shift -d (extra query bases); every byte is loaded
@@ -129,12 +136,19 @@ __device__ int estimate_rows(const uint8_t* qs, const uint8_t* ts, int Lq, int L
         dd = d;
       }
     }
-    if (nq < 0) return imin(pt + stop + 1, cap);
+    if (nq < 0) {
+      best = mx;
+      return imin(pt + stop + 1, cap);
+    }
     base = mx - P.o_del - dd * P.e_del;
-    if (base <= 0) return cap;
+    if (base <= 0) {
+      best = mx;
+      return cap;
+    }
     pq = nq;
     pt = nt;
   }
+  best = mx;
   return cap;
 }
 
@@ -208,6 +222,7 @@ k_prep(int64_t n, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
     // by the band (no row past qlen + w + 1 has a cell): pairs that end
     // early then share tiles, so the lanes of a tile finish together.
     int rows_est = imin(tl, ql + band_cap(P, ql) + 1);
+    int walk_best = 0;  // best score of the walk (a path the DP also scores)
     unsigned long long walk = __ballot(ok && ql > 192 && ql <= 256);
     while (walk) {
       const int l = __builtin_ctzll(walk);
@@ -216,8 +231,12 @@ k_prep(int64_t n, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
       const int wlq = __shfl(ql, l, 64), wlt = __shfl(tl, l, 64);
       const int wh = __shfl(hh, l, 64), wp = __shfl(p, l, 64);
       const int wcap = __shfl(rows_est, l, 64);
-      const int r = estimate_rows(q + wq, t + wt, wlq, wlt, wh, kp[wp], wcap);
-      if (lane == l) rows_est = r;
+      int wbest = 0;
+      const int r = estimate_rows(q + wq, t + wt, wlq, wlt, wh, kp[wp], wcap, wbest);
+      if (lane == l) {
+        rows_est = r;
+        walk_best = wbest;
+      }
     }
     uint32_t key = 0;
     if (ok) {
@@ -228,8 +247,10 @@ k_prep(int64_t n, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
       if (min_bits >= 32) wd = W32;
       // 16-bit pairs start at 8 bits when the seed itself leaves room
       const int slack = P.amax - P.oe_del > 0 ? P.amax - P.oe_del : 0;
-      const bool spec8 =
-          wd == W8 || (spec16 && wd == W16 && min_bits < 16 && hh + slack <= 255);
+      // (not when the walk already scored past what 8-bit records hold:
+      // the pair would only be rerun)
+      const bool spec8 = wd == W8 || (spec16 && wd == W16 && min_bits < 16 &&
+                                      hh + slack <= 255 && walk_best + slack < 255);
       int cls, cap;
       if (ql > 256) {
         cls = CLS_LONG;
