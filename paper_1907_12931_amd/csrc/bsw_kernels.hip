@@ -281,6 +281,8 @@ k_prep(int64_t n, const uint8_t* __restrict__ q, const uint8_t* __restrict__ t,
 
 // Every byte of q[off[0] .. off[n]) must be a code 0..4; a bad byte names
 // the pair that holds it (binary search over the offsets).
+__device__ __forceinline__ uint64_t imin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
 __global__ void k_codes(const uint8_t* __restrict__ s,
                         const uint64_t* __restrict__ off, int64_t n,
                         Status* st) {
@@ -288,30 +290,31 @@ __global__ void k_codes(const uint8_t* __restrict__ s,
   if (hi <= lo) return;
   const uint64_t len = hi - lo;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  // 4 bytes per step; the leading bytes up to a 4-byte boundary and the
+  // 16 bytes per step; the leading bytes up to a 16-byte boundary and the
   // tail are checked one by one
-  const uint64_t head = (4 - ((uintptr_t)(s + lo) & 3)) & 3;
+  const uint64_t head = (16 - ((uintptr_t)(s + lo) & 15)) & 15;
   const uint64_t h = head < len ? head : len;
-  const uint64_t nw = (len - h) >> 2;
-  const uint32_t* w = (const uint32_t*)(s + lo + h);
+  const uint64_t nv = (len - h) >> 4;
+  const uint4* w = (const uint4*)(s + lo + h);
   const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   uint64_t badpos = ~0ull;
-  for (uint64_t i = tid; i < nw; i += stride) {
-    const uint32_t v = w[i];
+  for (uint64_t i = tid; i < nv; i += stride) {
+    const uint4 v4 = w[i];
+    const uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
     // a byte is > 4 iff (byte + 0x7b) has bit 7 set, for bytes <= 0x84;
     // bytes >= 0x80 are caught by their own top bit
-    const uint32_t t = ((v & 0x7f7f7f7fu) + 0x7b7b7b7bu) | v;
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t |= ((v[k] & 0x7f7f7f7fu) + 0x7b7b7b7bu) | v[k];
     if (t & 0x80808080u) {
-      for (int b = 0; b < 4; ++b)
-        if (((v >> (8 * b)) & 0xffu) > 4) {
-          badpos = lo + h + i * 4 + b;
-          break;
-        }
+#pragma unroll
+      for (int b = 15; b >= 0; --b)
+        if (((v[b >> 2] >> (8 * (b & 3))) & 0xffu) > 4) badpos = imin64(badpos, lo + h + i * 16 + b);
     }
   }
-  if (tid < h && s[lo + tid] > 4) badpos = lo + tid;
-  const uint64_t tail = h + nw * 4;
-  if (tid < len - tail && s[lo + tail + tid] > 4) badpos = lo + tail + tid;
+  if (tid < h && s[lo + tid] > 4) badpos = imin64(badpos, lo + tid);
+  const uint64_t tail = h + nv * 16;
+  if (tid < len - tail && s[lo + tail + tid] > 4) badpos = imin64(badpos, lo + tail + tid);
   if (badpos != ~0ull) {
     int64_t a = 0, b = n - 1;  // largest k with off[k] <= badpos
     while (a < b) {
